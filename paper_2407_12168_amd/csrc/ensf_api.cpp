@@ -1,0 +1,761 @@
+// Host side of libensf: argument validation, workspace layout, grouped launches of the
+// pseudo-time loop (eager or as one captured hipGraph), status reporting, autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ensf.h"
+#include "ensf_internal.h"
+
+namespace ensf {
+hipError_t set_softmax_smem_limit(size_t bytes);
+}
+
+using namespace ensf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct TileChoice {
+  int gram = kGram128;
+  int wx = kWx128;
+  double split_scale = 1.0;  // multiplies the default split-K count
+};
+
+struct GraphKey {
+  int prec = -1, gram = -1, wx = -1, np = -1, gtot = -1, rtot = -1, wtot = -1, kmax = -1, ldn = -1;
+  const void* desc = nullptr;
+  const void* pre = nullptr;
+  const void* counters = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return prec == o.prec && gram == o.gram && wx == o.wx && np == o.np && gtot == o.gtot &&
+           rtot == o.rtot && wtot == o.wtot && kmax == o.kmax && ldn == o.ldn && desc == o.desc &&
+           pre == o.pre && counters == o.counters;
+  }
+};
+
+std::string tune_key(int prec, int64_t n, int64_t mp, int64_t d) {
+  auto bucket = [](int64_t v) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= v) ++b;
+    return b;
+  };
+  char buf[96];
+  snprintf(buf, sizeof buf, "gfx950/p%d/n%d/m%d/d%d", prec, bucket(n), bucket(mp), bucket(d));
+  return buf;
+}
+
+}  // namespace
+
+struct ensf_ctx {
+  ensf_options opt{};
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // descriptor table + prefix arrays: device copy and pinned host staging
+  char* d_tab = nullptr;
+  char* h_tab = nullptr;
+  size_t tab_bytes = 0;
+  hipEvent_t tab_event = nullptr;
+  bool tab_event_pending = false;
+  unsigned long long* d_counters = nullptr;  // [0] non-finite values, [1] bad obs indices
+  hipStream_t cap_stream = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_last_stream = false;
+  GraphKey gkey;
+  hipGraphExec_t gexec = nullptr;
+  std::map<std::string, TileChoice> tune;
+  std::string tune_path;
+  size_t softmax_smem_set = 0;
+  // phase timing (ensf_profile_phases)
+  bool profile = false;
+  std::vector<hipEvent_t> events;   // pool, 4 per pseudo-step of a profiled call
+  std::vector<std::pair<int, int>> pending;  // (first event index, steps) per profiled call
+  double phase_ms[3] = {0, 0, 0};
+  int64_t phase_count = 0;
+  size_t events_used = 0;
+};
+
+namespace {
+
+ensf_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? ENSF_ENOMEM : ENSF_EHIP; }
+
+#define HIP_TRY(expr)                               \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return hip_fail(_e);      \
+  } while (0)
+
+struct Plan {
+  std::vector<ProbDev> desc;
+  std::vector<int32_t> pre_gram, pre_rows, pre_wx;
+  TileChoice tiles;
+  int kmax = 0;
+  int max_ldn = 0;
+  size_t ws_needed = 0;
+};
+
+ensf_status validate(const ensf_problem& p) {
+  if (!p.d_prior || !p.d_post) return ENSF_EINVAL;
+  if (p.n_members < 1 || p.n_members > kMaxMembers) return ENSF_EINVAL;
+  if (p.n_particles < 1 || p.dim < 1 || p.n_steps < 1) return ENSF_EINVAL;
+  if ((int64_t)p.dim * 4 / 4 != p.dim || p.dim > (int64_t(1) << 34)) return ENSF_EINVAL;
+  if (p.n_obs < 0) return ENSF_EINVAL;
+  if (p.n_obs > 0) {
+    if (!p.d_obs_idx || !p.d_obs_val) return ENSF_EINVAL;
+    if (!(p.obs_sigma > 0.0f) || !std::isfinite(p.obs_sigma)) return ENSF_EINVAL;
+  }
+  const char* a0 = reinterpret_cast<const char*>(p.d_prior);
+  const char* a1 = a0 + (size_t)p.n_members * p.dim * sizeof(float);
+  const char* b0 = reinterpret_cast<const char*>(p.d_post);
+  const char* b1 = b0 + (size_t)p.n_particles * p.dim * sizeof(float);
+  if (a0 < b1 && b0 < a1) return ENSF_EINVAL;
+  return ENSF_OK;
+}
+
+TileChoice heuristic_tiles(int64_t n, int64_t mp) {
+  TileChoice c;
+  const int64_t mn = std::min(n, mp);
+  c.gram = mn >= 128 ? kGram128 : mn >= 48 ? kGram64 : kGram32;
+  c.wx = mp >= 128 ? kWx128 : mp >= 48 ? kWx64 : kWx32;
+  return c;
+}
+
+// Lays out one problem's workspace at offset `off` (bytes) and fills its descriptor.
+size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileChoice& tc,
+                      int obs_op, double eps, size_t off, char* base) {
+  auto take = [&](size_t bytes) {
+    off = round_up(off, kAlign);
+    char* ptr = base ? base + off : nullptr;
+    off += bytes;
+    return ptr;
+  };
+  P = ProbDev{};
+  P.X = p.d_prior;
+  P.post = p.d_post;
+  P.obs_idx = p.d_obs_idx;
+  P.obs_val = p.d_obs_val;
+  P.N = p.n_members;
+  P.Mp = p.n_particles;
+  P.d = p.dim;
+  P.n_obs = p.n_obs;
+  P.K = p.n_steps;
+  P.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  P.seed_hi = (uint32_t)(p.seed >> 32);
+  P.filter = p.filter_id;
+  P.inv_sig2 = p.n_obs > 0 ? (float)(1.0 / ((double)p.obs_sigma * (double)p.obs_sigma)) : 0.0f;
+  P.obs_op = obs_op;
+  P.eps = eps;
+  P.t_score = 1.0;
+  P.Mp_pad = (int32_t)round_up(P.Mp, kRowPad);
+  P.N_pad = (int32_t)round_up(P.N, kRowPad);
+  P.ldn = P.N_pad;
+  P.ldz = round_up(P.d, kColPad);
+
+  const int bm = gram_bm(tc.gram), bn = gram_bn(tc.gram);
+  P.gram_tm = (int32_t)ceil_div(P.Mp, bm);
+  P.gram_tn = (int32_t)ceil_div(P.N, bn);
+  const int64_t tiles = (int64_t)P.gram_tm * P.gram_tn;
+  // split-K: enough workgroups to fill the device, chunks of at least 4 k-steps, and the
+  // partial sums no larger than a quarter of the Gram's operand bytes
+  int64_t s = ceil_div(1024, tiles);
+  s = std::min<int64_t>(s, P.ldz / (4 * kBK));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, (P.Mp + P.N) * P.ldz / (4 * (int64_t)P.Mp * P.N)));
+  s = std::max<int64_t>(1, (int64_t)std::llround(s * tc.split_scale));
+  s = std::min<int64_t>(s, P.ldz / kBK);
+  P.kchunk = round_up(ceil_div(P.ldz, s), kBK);
+  P.S = (int32_t)ceil_div(P.ldz, P.kchunk);
+  P.wx_tm = (int32_t)ceil_div(P.Mp, wx_bm(tc.wx));
+  P.wx_tn = (int32_t)ceil_div(P.d, wx_bn(tc.wx));
+
+  P.Z = reinterpret_cast<float*>(take((size_t)P.Mp_pad * P.ldz * 4));
+  if (prec == kFP32) {
+    P.Xf = reinterpret_cast<float*>(take((size_t)P.N_pad * P.ldz * 4));
+  } else {
+    P.Xh = reinterpret_cast<uint16_t*>(take((size_t)P.N_pad * P.ldz * 2));
+    P.Xl = reinterpret_cast<uint16_t*>(take((size_t)P.N_pad * P.ldz * 2));
+    P.XTh = reinterpret_cast<uint16_t*>(take((size_t)P.ldz * P.ldn * 2));
+    P.XTl = reinterpret_cast<uint16_t*>(take((size_t)P.ldz * P.ldn * 2));
+  }
+  P.xnorm = reinterpret_cast<float*>(take((size_t)P.ldn * 4));
+  P.A = reinterpret_cast<float*>(take((size_t)P.ldz * 4));
+  P.B = reinterpret_cast<float*>(take((size_t)P.ldz * 4));
+  P.part = reinterpret_cast<float*>(take((size_t)P.S * P.Mp_pad * P.ldn * 4));
+  if (prec == kFP32) {
+    P.W = reinterpret_cast<float*>(take((size_t)P.Mp_pad * P.ldn * 4));
+  } else {
+    P.Wh = reinterpret_cast<uint16_t*>(take((size_t)P.Mp_pad * P.ldn * 2));
+    P.Wl = reinterpret_cast<uint16_t*>(take((size_t)P.Mp_pad * P.ldn * 2));
+  }
+  return round_up(off, kAlign);
+}
+
+ensf_status ensure_workspace(ensf_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return ENSF_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (c->ws) HIP_TRY(hipFree(c->ws));
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  const size_t want = round_up(bytes + bytes / 8, 1 << 20);
+  HIP_TRY(hipMalloc(&c->ws, want));
+  c->ws_bytes = want;
+  return ENSF_OK;
+}
+
+ensf_status ensure_table(ensf_ctx* c, size_t bytes) {
+  if (bytes <= c->tab_bytes) return ENSF_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (c->d_tab) HIP_TRY(hipFree(c->d_tab));
+  if (c->h_tab) HIP_TRY(hipHostFree(c->h_tab));
+  c->d_tab = nullptr;
+  c->h_tab = nullptr;
+  c->tab_bytes = 0;
+  const size_t want = round_up(bytes * 2, 4096);
+  HIP_TRY(hipMalloc(&c->d_tab, want));
+  HIP_TRY(hipHostMalloc(&c->h_tab, want, hipHostMallocDefault));
+  c->tab_bytes = want;
+  c->tab_event_pending = false;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gkey = GraphKey{};
+  }
+  return ENSF_OK;
+}
+
+TileChoice choose_tiles(ensf_ctx* c, int prec, const std::vector<ensf_problem>& probs) {
+  // the problem with the most work decides the shapes of a grouped launch
+  size_t best = 0;
+  double work = -1;
+  for (size_t f = 0; f < probs.size(); ++f) {
+    const double w = (double)probs[f].n_members * probs[f].n_particles * probs[f].dim;
+    if (w > work) { work = w; best = f; }
+  }
+  const ensf_problem& p = probs[best];
+  auto it = c->tune.find(tune_key(prec, p.n_members, p.n_particles, p.dim));
+  if (it != c->tune.end()) return it->second;
+  return heuristic_tiles(p.n_members, p.n_particles);
+}
+
+ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan,
+                       const TileChoice* force) {
+  const int prec = c->opt.precision;
+  plan.tiles = force ? *force : choose_tiles(c, prec, probs);
+  const int np = (int)probs.size();
+  plan.desc.resize(np);
+  plan.pre_gram.assign(np + 1, 0);
+  plan.pre_rows.assign(np + 1, 0);
+  plan.pre_wx.assign(np + 1, 0);
+  size_t off = 0;
+  plan.kmax = 0;
+  plan.max_ldn = 0;
+  for (int f = 0; f < np; ++f) {
+    ProbDev& P = plan.desc[f];
+    off = layout_problem(P, probs[f], prec, plan.tiles, c->opt.obs_op, c->opt.eps_alpha, off,
+                         nullptr);
+    const int64_t g = (int64_t)P.gram_tm * P.gram_tn * P.S;
+    const int64_t w = (int64_t)P.wx_tm * P.wx_tn;
+    if (plan.pre_gram[f] + g > INT32_MAX || plan.pre_wx[f] + w > INT32_MAX) return ENSF_EINVAL;
+    plan.pre_gram[f + 1] = plan.pre_gram[f] + (int32_t)g;
+    plan.pre_rows[f + 1] = plan.pre_rows[f] + P.Mp;
+    plan.pre_wx[f + 1] = plan.pre_wx[f] + (int32_t)w;
+    plan.kmax = std::max(plan.kmax, P.K);
+    plan.max_ldn = std::max(plan.max_ldn, P.ldn);
+  }
+  plan.ws_needed = off;
+  return ENSF_OK;
+}
+
+// Second pass: real pointers once the workspace exists.
+void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) {
+  size_t off = 0;
+  for (size_t f = 0; f < probs.size(); ++f)
+    off = layout_problem(plan.desc[f], probs[f], c->opt.precision, plan.tiles, c->opt.obs_op,
+                         c->opt.eps_alpha, off, c->ws);
+}
+
+struct Uploaded {
+  GroupedLaunch gram, rows, wx;
+};
+
+ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& u) {
+  const int np = (int)plan.desc.size();
+  const size_t desc_bytes = round_up(sizeof(ProbDev) * np, 256);
+  const size_t pre_bytes = round_up(sizeof(int32_t) * (np + 1), 256);
+  ensf_status st = ensure_table(c, desc_bytes + 3 * pre_bytes);
+  if (st != ENSF_OK) return st;
+  if (c->tab_event_pending) HIP_TRY(hipEventSynchronize(c->tab_event));
+  memcpy(c->h_tab, plan.desc.data(), sizeof(ProbDev) * np);
+  memcpy(c->h_tab + desc_bytes, plan.pre_gram.data(), sizeof(int32_t) * (np + 1));
+  memcpy(c->h_tab + desc_bytes + pre_bytes, plan.pre_rows.data(), sizeof(int32_t) * (np + 1));
+  memcpy(c->h_tab + desc_bytes + 2 * pre_bytes, plan.pre_wx.data(), sizeof(int32_t) * (np + 1));
+  HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, desc_bytes + 3 * pre_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(c->tab_event, s));
+  c->tab_event_pending = true;
+  const ProbDev* d = reinterpret_cast<const ProbDev*>(c->d_tab);
+  const int32_t* pg = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes);
+  const int32_t* pr = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes + pre_bytes);
+  const int32_t* pw = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes + 2 * pre_bytes);
+  u.gram = GroupedLaunch{d, pg, np, plan.pre_gram[np]};
+  u.rows = GroupedLaunch{d, pr, np, plan.pre_rows[np]};
+  u.wx = GroupedLaunch{d, pw, np, plan.pre_wx[np]};
+  return ENSF_OK;
+}
+
+ensf_status zero_problem(const ProbDev& P, int prec, hipStream_t s) {
+  HIP_TRY(hipMemsetAsync(P.Z, 0, (size_t)P.Mp_pad * P.ldz * 4, s));
+  if (prec == kFP32) {
+    HIP_TRY(hipMemsetAsync(P.Xf, 0, (size_t)P.N_pad * P.ldz * 4, s));
+    HIP_TRY(hipMemsetAsync(P.W, 0, (size_t)P.Mp_pad * P.ldn * 4, s));
+  } else {
+    HIP_TRY(hipMemsetAsync(P.Xh, 0, (size_t)P.N_pad * P.ldz * 2, s));
+    HIP_TRY(hipMemsetAsync(P.Xl, 0, (size_t)P.N_pad * P.ldz * 2, s));
+    HIP_TRY(hipMemsetAsync(P.Wh, 0, (size_t)P.Mp_pad * P.ldn * 2, s));
+    HIP_TRY(hipMemsetAsync(P.Wl, 0, (size_t)P.Mp_pad * P.ldn * 2, s));
+  }
+  HIP_TRY(hipMemsetAsync(P.xnorm, 0, (size_t)P.ldn * 4, s));
+  HIP_TRY(hipMemsetAsync(P.A, 0, (size_t)P.ldz * 4, s));
+  HIP_TRY(hipMemsetAsync(P.B, 0, (size_t)P.ldz * 4, s));
+  return ENSF_OK;
+}
+
+ensf_status prep_problem(ensf_ctx* c, const ProbDev& P, bool score_mode, hipStream_t s) {
+  const int prec = c->opt.precision;
+  ensf_status st = zero_problem(P, prec, s);
+  if (st != ENSF_OK) return st;
+  HIP_TRY(launch_densify(P, c->d_counters + 1, s));
+  HIP_TRY(launch_prep_rows(prec, P, s));
+  if (prec != kFP32) HIP_TRY(launch_transpose(P, s));
+  if (score_mode)
+    HIP_TRY(launch_load_z(P, s));
+  else
+    HIP_TRY(launch_init_z(P, s));
+  return ENSF_OK;
+}
+
+ensf_status ensure_softmax_smem(ensf_ctx* c, int max_ldn) {
+  const size_t bytes = (size_t)max_ldn * sizeof(double);
+  if (bytes > 64 * 1024 && bytes > c->softmax_smem_set) {
+    HIP_TRY(set_softmax_smem_limit(bytes));
+    c->softmax_smem_set = bytes;
+  }
+  return ENSF_OK;
+}
+
+ensf_status enqueue_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStream_t s) {
+  const int prec = c->opt.precision;
+  for (int k = 0; k < plan.kmax; ++k) {
+    HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, k, s));
+    HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
+    HIP_TRY(launch_wx(prec, plan.tiles.wx, false, u.wx, k, c->d_counters, s));
+  }
+  return ENSF_OK;
+}
+
+ensf_status collect_phase_times(ensf_ctx* c) {
+  for (const auto& pr : c->pending) {
+    HIP_TRY(hipEventSynchronize(c->events[pr.first + 4 * pr.second - 1]));
+    for (int k = 0; k < pr.second; ++k) {
+      const int b = pr.first + 4 * k;
+      for (int ph = 0; ph < 3; ++ph) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, c->events[b + ph], c->events[b + ph + 1]));
+        c->phase_ms[ph] += ms;
+      }
+    }
+    c->phase_count += pr.second;
+  }
+  c->pending.clear();
+  c->events_used = 0;
+  return ENSF_OK;
+}
+
+ensf_status enqueue_steps_profiled(ensf_ctx* c, const Plan& plan, const Uploaded& u,
+                                   hipStream_t s) {
+  const size_t need = c->events_used + 4 * (size_t)plan.kmax;
+  while (c->events.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  const int prec = c->opt.precision;
+  const size_t first = c->events_used;
+  for (int k = 0; k < plan.kmax; ++k) {
+    hipEvent_t* ev = &c->events[first + 4 * k];
+    HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, k, s));
+    HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
+    HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(launch_wx(prec, plan.tiles.wx, false, u.wx, k, c->d_counters, s));
+    HIP_TRY(hipEventRecord(ev[3], s));
+  }
+  c->events_used = need;
+  c->pending.emplace_back((int)first, plan.kmax);
+  return ENSF_OK;
+}
+
+ensf_status run_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStream_t s) {
+  if (c->profile) {
+    if (c->events_used > 4096) {
+      ensf_status st = collect_phase_times(c);
+      if (st != ENSF_OK) return st;
+    }
+    return enqueue_steps_profiled(c, plan, u, s);
+  }
+  if (!c->opt.use_graph) return enqueue_steps(c, plan, u, s);
+  GraphKey key;
+  key.prec = c->opt.precision;
+  key.gram = plan.tiles.gram;
+  key.wx = plan.tiles.wx;
+  key.np = u.gram.np;
+  key.gtot = u.gram.total;
+  key.rtot = u.rows.total;
+  key.wtot = u.wx.total;
+  key.kmax = plan.kmax;
+  key.ldn = plan.max_ldn;
+  key.desc = u.gram.desc;
+  key.pre = u.gram.pre;
+  key.counters = c->d_counters;
+  if (!(c->gexec && key == c->gkey)) {
+    if (c->gexec) {
+      HIP_TRY(hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    ensf_status st = enqueue_steps(c, plan, u, c->cap_stream);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st != ENSF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(e);
+    }
+    c->gkey = key;
+  }
+  HIP_TRY(hipGraphLaunch(c->gexec, s));
+  return ENSF_OK;
+}
+
+ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, hipStream_t s,
+                          const TileChoice* force) {
+  for (const auto& p : probs) {
+    ensf_status st = validate(p);
+    if (st != ENSF_OK) return st;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  Plan plan;
+  ensf_status st = build_plan(c, probs, plan, force);
+  if (st != ENSF_OK) return st;
+  st = ensure_workspace(c, plan.ws_needed);
+  if (st != ENSF_OK) return st;
+  bind_plan(c, probs, plan);
+  st = ensure_softmax_smem(c, plan.max_ldn);
+  if (st != ENSF_OK) return st;
+  Uploaded u;
+  st = upload_plan(c, plan, s, u);
+  if (st != ENSF_OK) return st;
+  for (const ProbDev& P : plan.desc) {
+    st = prep_problem(c, P, false, s);
+    if (st != ENSF_OK) return st;
+  }
+  st = run_steps(c, plan, u, s);
+  if (st != ENSF_OK) return st;
+  for (const ProbDev& P : plan.desc) {
+    if (c->opt.spread_relax > 0.0 && P.Mp > 1 && P.N > 1)
+      HIP_TRY(launch_relax(P, c->opt.spread_relax, s));
+    HIP_TRY(launch_store_post(P, s));
+  }
+  c->last_stream = s;
+  c->has_last_stream = true;
+  return ENSF_OK;
+}
+
+// ----- tune cache: a flat JSON object {"key": [gram, wx, split_scale], ...}
+void load_tune_cache(ensf_ctx* c) {
+  if (c->tune_path.empty()) return;
+  FILE* fp = fopen(c->tune_path.c_str(), "r");
+  if (!fp) return;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, fp)) > 0) txt.append(buf, n);
+  fclose(fp);
+  size_t pos = 0;
+  while ((pos = txt.find('"', pos)) != std::string::npos) {
+    const size_t end = txt.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = txt.substr(pos + 1, end - pos - 1);
+    TileChoice tc;
+    if (sscanf(txt.c_str() + end + 1, " : [ %d , %d , %lf ]", &tc.gram, &tc.wx, &tc.split_scale) == 3 &&
+        tc.gram >= 0 && tc.gram < kNumGram && tc.wx >= 0 && tc.wx < kNumWx)
+      c->tune[key] = tc;
+    pos = end + 1;
+  }
+}
+
+void save_tune_cache(ensf_ctx* c) {
+  if (c->tune_path.empty()) return;
+  FILE* fp = fopen(c->tune_path.c_str(), "w");
+  if (!fp) return;
+  fprintf(fp, "{\n");
+  size_t i = 0;
+  for (const auto& kv : c->tune)
+    fprintf(fp, "  \"%s\": [%d, %d, %.3f]%s\n", kv.first.c_str(), kv.second.gram, kv.second.wx,
+            kv.second.split_scale, ++i < c->tune.size() ? "," : "");
+  fprintf(fp, "}\n");
+  fclose(fp);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ensf_default_options(ensf_options* opt) {
+  if (!opt) return;
+  opt->precision = ENSF_PREC_FP32;
+  opt->obs_op = ENSF_OBS_ARCTAN;
+  opt->eps_alpha = 0.05;
+  opt->spread_relax = 0.0;
+  opt->use_graph = 1;
+  opt->device = 0;
+  opt->tune_cache = nullptr;
+}
+
+ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out) {
+  if (!out) return ENSF_EINVAL;
+  *out = nullptr;
+  ensf_options o;
+  ensf_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1) return ENSF_EINVAL;
+  if (!(o.eps_alpha > 0.0 && o.eps_alpha < 1.0)) return ENSF_EINVAL;
+  if (!(o.spread_relax >= 0.0 && o.spread_relax <= 1.0)) return ENSF_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ENSF_EHIP;
+  if (o.device < 0 || o.device >= ndev) return ENSF_EINVAL;
+  HIP_TRY(hipSetDevice(o.device));
+  ensf_ctx* c = new ensf_ctx();
+  c->opt = o;
+  c->device = o.device;
+  const char* tp = o.tune_cache ? o.tune_cache : getenv("ENSF_TUNE_CACHE");
+  if (tp) c->tune_path = tp;
+  c->opt.tune_cache = nullptr;
+  hipError_t e = hipMalloc(&c->d_counters, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_event, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    ensf_destroy(c);
+    return hip_fail(e);
+  }
+  load_tune_cache(c);
+  *out = c;
+  return ENSF_OK;
+}
+
+ensf_status ensf_analysis(ensf_ctx* ctx, const float* d_prior, int32_t n_members, int64_t dim,
+                          float* d_post, int32_t n_particles, const int32_t* d_obs_idx,
+                          const float* d_obs_val, int64_t n_obs, float obs_sigma,
+                          int32_t n_steps, uint64_t seed, uint32_t filter_id, void* stream) {
+  if (!ctx) return ENSF_EINVAL;
+  ensf_problem p{d_prior, n_members, dim, d_post, n_particles, d_obs_idx, d_obs_val,
+                 n_obs, obs_sigma, n_steps, seed, filter_id};
+  return analysis_impl(ctx, {p}, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+ensf_status ensf_analysis_batched(ensf_ctx* ctx, const ensf_problem* probs, int32_t n_problems,
+                                  void* stream) {
+  if (!ctx || !probs || n_problems < 1) return ENSF_EINVAL;
+  std::vector<ensf_problem> v(probs, probs + n_problems);
+  return analysis_impl(ctx, v, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, int64_t dim,
+                       const float* d_z, int32_t n_particles, const int32_t* d_obs_idx,
+                       const float* d_obs_val, int64_t n_obs, float obs_sigma, double t,
+                       float* d_score, float* d_weights, void* stream) {
+  if (!ctx || !d_z || !d_score) return ENSF_EINVAL;
+  if (!(t > 0.0 && t <= 1.0)) return ENSF_EINVAL;
+  ensf_problem p{d_prior, n_members, dim, d_score, n_particles, d_obs_idx, d_obs_val,
+                 n_obs, obs_sigma, 1, 0, 0};
+  ensf_status st = validate(p);
+  if (st != ENSF_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::vector<ensf_problem> probs{p};
+  Plan plan;
+  st = build_plan(ctx, probs, plan, nullptr);
+  if (st != ENSF_OK) return st;
+  st = ensure_workspace(ctx, plan.ws_needed);
+  if (st != ENSF_OK) return st;
+  bind_plan(ctx, probs, plan);
+  ProbDev& P = plan.desc[0];
+  P.zin = d_z;
+  P.score_out = d_score;
+  P.weights_out = d_weights;
+  P.post = nullptr;
+  P.t_score = t;
+  st = ensure_softmax_smem(ctx, plan.max_ldn);
+  if (st != ENSF_OK) return st;
+  Uploaded u;
+  st = upload_plan(ctx, plan, s, u);
+  if (st != ENSF_OK) return st;
+  st = prep_problem(ctx, P, true, s);
+  if (st != ENSF_OK) return st;
+  const int prec = ctx->opt.precision;
+  HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, -1, s));
+  HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
+  HIP_TRY(launch_wx(prec, plan.tiles.wx, true, u.wx, -1, ctx->d_counters, s));
+  ctx->last_stream = s;
+  ctx->has_last_stream = true;
+  return ENSF_OK;
+}
+
+ensf_status ensf_rng_normal(uint64_t seed, uint32_t filter_id, uint32_t step, uint32_t particle,
+                            int64_t n, float* d_out, uint32_t* d_raw_words, void* stream) {
+  if (!d_out || n < 1 || n > (int64_t(1) << 34)) return ENSF_EINVAL;
+  HIP_TRY(launch_rng_normal(seed, filter_id, step, particle, n, d_out, d_raw_words,
+                            reinterpret_cast<hipStream_t>(stream)));
+  return ENSF_OK;
+}
+
+ensf_status ensf_ensemble_stats(const float* d_ens, int32_t n, int64_t dim, float* d_mean,
+                                float* d_spread, void* stream) {
+  if (!d_ens || !d_mean || !d_spread || n < 2 || dim < 1) return ENSF_EINVAL;
+  HIP_TRY(launch_stats(d_ens, n, dim, d_mean, d_spread, reinterpret_cast<hipStream_t>(stream)));
+  return ENSF_OK;
+}
+
+ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count) {
+  if (!ctx) return ENSF_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->has_last_stream) HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+  unsigned long long h[2] = {0, 0};
+  HIP_TRY(hipMemcpy(h, ctx->d_counters, sizeof h, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(ctx->d_counters, 0, sizeof h));
+  if (nonfinite_count) *nonfinite_count = (int64_t)h[0];
+  if (h[1]) return ENSF_EINVAL;
+  if (h[0]) return ENSF_ENONFINITE;
+  return ENSF_OK;
+}
+
+ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream) {
+  if (!ctx || !prob) return ENSF_EINVAL;
+  ensf_status st = validate(*prob);
+  if (st != ENSF_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(ctx->device));
+  ensf_problem p = *prob;
+  p.n_steps = std::min(p.n_steps, 8);
+  std::vector<ensf_problem> probs{p};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  TileChoice best;
+  float best_ms = INFINITY;
+  const int use_graph = ctx->opt.use_graph;
+  ctx->opt.use_graph = 0;
+  const double scales[] = {0.5, 1.0, 2.0};
+  for (int gc = 0; gc < kNumGram; ++gc)
+    for (int wc = 0; wc < kNumWx; ++wc)
+      for (double sc : scales) {
+        TileChoice tc;
+        tc.gram = gc;
+        tc.wx = wc;
+        tc.split_scale = sc;
+        float ms_sum = 0.0f;
+        for (int rep = 0; rep < 3 && st == ENSF_OK; ++rep) {
+          st = analysis_impl(ctx, probs, s, &tc);  // warm-up on rep 0
+          if (st != ENSF_OK || rep == 0) continue;
+          if (hipEventRecord(e0, s) != hipSuccess) st = ENSF_EHIP;
+          if (st == ENSF_OK) st = analysis_impl(ctx, probs, s, &tc);
+          if (st == ENSF_OK && hipEventRecord(e1, s) != hipSuccess) st = ENSF_EHIP;
+          if (st == ENSF_OK && hipEventSynchronize(e1) != hipSuccess) st = ENSF_EHIP;
+          float ms = 0;
+          if (st == ENSF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = ENSF_EHIP;
+          ms_sum += ms;
+        }
+        if (st != ENSF_OK) break;
+        if (ms_sum < best_ms) {
+          best_ms = ms_sum;
+          best = tc;
+        }
+      }
+  ctx->opt.use_graph = use_graph;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ENSF_OK) return st;
+  ctx->tune[tune_key(ctx->opt.precision, p.n_members, p.n_particles, p.dim)] = best;
+  save_tune_cache(ctx);
+  return ENSF_OK;
+}
+
+ensf_status ensf_profile_phases(ensf_ctx* ctx, int32_t enable) {
+  if (!ctx) return ENSF_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ensf_status st = collect_phase_times(ctx);
+  if (st != ENSF_OK) return st;
+  ctx->profile = enable != 0;
+  for (double& m : ctx->phase_ms) m = 0;
+  ctx->phase_count = 0;
+  return ENSF_OK;
+}
+
+ensf_status ensf_phase_times(ensf_ctx* ctx, double* ms, int64_t* count) {
+  if (!ctx || !ms) return ENSF_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ensf_status st = collect_phase_times(ctx);
+  if (st != ENSF_OK) return st;
+  for (int i = 0; i < 3; ++i) ms[i] = ctx->phase_ms[i];
+  if (count) *count = ctx->phase_count;
+  return ENSF_OK;
+}
+
+ensf_status ensf_destroy(ensf_ctx* ctx) {
+  if (!ctx) return ENSF_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->d_tab) (void)hipFree(ctx->d_tab);
+  if (ctx->h_tab) (void)hipHostFree(ctx->h_tab);
+  if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->tab_event) (void)hipEventDestroy(ctx->tab_event);
+  delete ctx;
+  return ENSF_OK;
+}
+
+const char* ensf_status_string(ensf_status s) {
+  switch (s) {
+    case ENSF_OK: return "ok";
+    case ENSF_EINVAL: return "invalid argument";
+    case ENSF_ENOMEM: return "out of memory";
+    case ENSF_EHIP: return "HIP runtime error";
+    case ENSF_ENONFINITE: return "non-finite particle values";
+    case ENSF_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal descriptors shared by the HIP kernels and the host side of libensf.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ensf {
+
+enum Prec : int { kFP32 = 0, kBF16X3 = 1, kBF16 = 2 };
+enum ObsOp : int { kArctan = 0, kLinear = 1 };
+
+// Row and column paddings of every workspace matrix: rows of the particle and member
+// dimensions are padded to kRowPad, the state dimension to kColPad.  All tile shapes
+// divide these, so kernels never read outside the allocation, and the padding is zero.
+constexpr int kRowPad = 128;
+constexpr int kColPad = 128;
+constexpr int kMaxMembers = 16384;
+
+// One analysis problem as the kernels see it (device-resident table, one entry per
+// problem of a batched call).
+struct ProbDev {
+  // caller-owned
+  const float* X;           // N x d prior
+  float* post;              // Mp x d output
+  const int32_t* obs_idx;
+  const float* obs_val;
+  const float* zin;         // score mode: given particles (Mp x d)
+  float* score_out;         // score mode: score (Mp x d)
+  float* weights_out;       // score mode: weights (Mp x N), may be null
+  // workspace
+  float* Z;                 // Mp_pad x ldz particles (zero padded)
+  float* Xf;                // N_pad x ldz prior copy (FP32 form)
+  uint16_t* Xh;             // N_pad x ldz  bf16 hi (split forms)
+  uint16_t* Xl;             // N_pad x ldz  bf16 lo
+  uint16_t* XTh;            // ldz x ldn    transposed hi
+  uint16_t* XTl;            // ldz x ldn    transposed lo
+  float* xnorm;             // ldn  |x_j|^2
+  float* A;                 // ldz  sum y / sigma^2 per component
+  float* B;                 // ldz  count / sigma^2 per component
+  float* part;              // S x Mp_pad x ldn split-K Gram partials
+  float* W;                 // Mp_pad x ldn softmax weights (FP32 form)
+  uint16_t* Wh;             // Mp_pad x ldn (split forms)
+  uint16_t* Wl;
+  int64_t d, ldz, n_obs, kchunk;
+  int32_t N, Mp, Mp_pad, N_pad, ldn, S, K;
+  uint32_t seed_lo, seed_hi, filter;
+  float inv_sig2;
+  int32_t obs_op;
+  double eps, t_score;
+  int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
+  int32_t wx_tm, wx_tn;       // W.X tiles along particles, elements
+};
+
+// Per-step scalars in FP32, computed in FP64 from (t, eps) exactly as the oracle does.
+struct StepScalars {
+  float alpha, inv_beta2, b, sigma2, h, dt, cnoise;
+};
+
+// Prefix arrays of a grouped launch: tiles of problem f are [pre[f], pre[f+1]).
+struct GroupedLaunch {
+  const ProbDev* desc;
+  const int32_t* pre;
+  int32_t np;
+  int32_t total;
+};
+
+// Kernel-shape identifiers chosen by the host (heuristic or autotuner).
+enum GramCfg : int { kGram128 = 0, kGram64 = 1, kGram32 = 2, kNumGram = 3 };
+enum WxCfg : int { kWx128 = 0, kWx64 = 1, kWx32 = 2, kNumWx = 3 };
+
+inline int gram_bm(int c) { return c == kGram128 ? 128 : c == kGram64 ? 64 : 32; }
+inline int gram_bn(int c) { return gram_bm(c); }
+inline int wx_bm(int c) { return c == kWx128 ? 128 : c == kWx64 ? 64 : 32; }
+inline int wx_bn(int c) { return 128; }
+constexpr int kBK = 32;
+
+// Host-callable launchers (ensf_kernels.hip).
+hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipStream_t s);
+hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ldn, hipStream_t s);
+hipError_t launch_wx(int prec, int cfg, bool score_mode, const GroupedLaunch& g, int step,
+                     unsigned long long* nonfinite, hipStream_t s);
+hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s);
+hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s);
+hipError_t launch_transpose(const ProbDev& p, hipStream_t s);
+hipError_t launch_init_z(const ProbDev& p, hipStream_t s);
+hipError_t launch_load_z(const ProbDev& p, hipStream_t s);
+hipError_t launch_store_post(const ProbDev& p, hipStream_t s);
+hipError_t launch_relax(const ProbDev& p, double r, hipStream_t s);
+hipError_t launch_rng_normal(uint64_t seed, uint32_t filter, uint32_t step, uint32_t particle,
+                             int64_t n, float* out, uint32_t* raw, hipStream_t s);
+hipError_t launch_stats(const float* ens, int32_t n, int64_t d, float* mean, float* spread,
+                        hipStream_t s);
+
+}  // namespace ensf

@@ -1,0 +1,885 @@
+// HIP kernels of the EnSF analysis step for CDNA4 (gfx950).
+//
+// Per pseudo-step k of the reverse-time SDE (eq. 7) three grouped launches run:
+//   k_gram     G = Z X^T (particles x members), split-K over the state dimension with a
+//              fixed-order (deterministic) reduction: the squared distances of eq. 12 are
+//              |z|^2 - 2 alpha z.x + alpha^2 |x|^2 and only z.x needs a contraction.
+//   k_softmax  logits (alpha G_ij - alpha^2 |x_j|^2 / 2) / beta^2 (the |z_i|^2 term is the
+//              same for every j of a row and cancels in eq. 16), row max, exp, normalise.
+//   k_wx       xhat = W X on MFMA, then in the same kernel the damped posterior score of
+//              eq. 17 (prior score of eq. 15 plus h(t) times the likelihood score of the
+//              Gaussian of eq. 5), Philox4x32-10 + Box-Muller noise, and the
+//              Euler-Maruyama update of eq. 7, written back in place.
+// A launch covers the tiles of every problem of a batch; a tile finds its problem by a
+// binary search over the prefix array.
+//
+// Operands: FP32 form on v_mfma_f32_32x32x2_f32; split-BF16 form
+// (hi = bf16(x), lo = bf16(x - hi), products hi*hi + hi*lo + lo*hi) and plain BF16 on
+// v_mfma_f32_32x32x16_bf16, FP32 accumulation in both.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ensf_internal.h"
+
+namespace ensf {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// ----------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ int find_problem(const int32_t* pre, int np, int tile) {
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the device; this bijection
+// gives each XCD a contiguous range of logical tiles, so tiles that share operands
+// (adjacent in the logical order) share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int x = b & 7, local = b >> 3, per = G >> 3, rem = G & 7;
+  return x * per + min(x, rem) + local;
+}
+
+__device__ __forceinline__ double step_time(const ProbDev& P, int step) {
+  if (step < 0) return P.t_score;
+  const double dt = 1.0 / (double)P.K;
+  return 1.0 - (double)step * dt;
+}
+
+// Schedule of eq. 9 with alpha_t = 1 - t (1 - eps), beta_t^2 = t, damping h = 1 - t
+// (eq. 11), evaluated in FP64 and rounded once to FP32.
+__device__ __forceinline__ StepScalars step_scalars(double t, double eps, int K) {
+  const double alpha = 1.0 - t * (1.0 - eps);
+  const double beta2 = t;
+  const double b = -(1.0 - eps) / alpha;
+  const double sigma2 = 1.0 - 2.0 * b * beta2;
+  const double dt = 1.0 / (double)(K > 0 ? K : 1);
+  StepScalars s;
+  s.alpha = (float)alpha;
+  s.inv_beta2 = (float)(1.0 / beta2);
+  s.b = (float)b;
+  s.sigma2 = (float)sigma2;
+  s.h = (float)(1.0 - t);
+  s.dt = (float)dt;
+  s.cnoise = (float)sqrt(sigma2 * dt);
+  return s;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies with the
+// Weyl key schedule.
+struct Words4 { uint32_t w0, w1, w2, w3; };
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float u24(uint32_t r) {
+  return ((float)(r >> 8) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24, exact
+}
+
+// Box-Muller (1958): one pair of standard normals from two uniforms.
+__device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float& n0, float& n1) {
+  const float rad = sqrtf(-2.0f * logf(u24(ra)));
+  float s, c;
+  sincospif(2.0f * u24(rb), &s, &c);
+  n0 = rad * c;
+  n1 = rad * s;
+}
+
+__device__ __forceinline__ f32x4 normals4(uint32_t quad, uint32_t particle, uint32_t step,
+                                           const ProbDev& P) {
+  const Words4 w = philox4x32_10(quad, particle, step, P.filter, P.seed_lo, P.seed_hi);
+  float a, b, c, d;
+  box_muller(w.w0, w.w1, a, b);
+  box_muller(w.w2, w.w3, c, d);
+  return f32x4{a, b, c, d};
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(__bf16 h) { return __builtin_bit_cast(uint16_t, h); }
+
+// RNE split of an FP32 value into bf16 hi and lo (x - hi is exact in FP32).
+__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+  const __bf16 h = (__bf16)x;
+  hi = bf16_bits(h);
+  lo = bf16_bits((__bf16)(x - (float)h));
+}
+
+__device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
+  return (uint32_t)a | ((uint32_t)b << 16);
+}
+
+// Damped posterior score (eq. 17) of one component given xhat = sum_j w_j x_j.
+__device__ __forceinline__ float posterior_score(float z, float xh, float a, float b,
+                                                 const StepScalars& sc, int op) {
+  const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
+  const float lik = (op == kArctan) ? (a - b * atanf(z)) / (1.0f + z * z) : (a - b * z);
+  return prior + sc.h * lik;
+}
+
+// Euler-Maruyama step of the reverse-time SDE (eq. 7), backward in t.
+__device__ __forceinline__ float em_step(float z, float s, float xi, const StepScalars& sc) {
+  return z - (sc.b * z - sc.sigma2 * s) * sc.dt + sc.cnoise * xi;
+}
+
+// ----------------------------------------------------------------------------------------
+// MFMA tile machinery.  A workgroup of WGM x WGN waves computes a BM x BN tile with
+// BM = WGM*TM*32, BN = WGN*TN*32; each wave owns TM x TN blocks of 32 x 32.
+// 32x32 accumulator layout (both MFMA kinds): lane l, register r holds
+// row (r/4)*8 + (l/32)*4 + r%4, column l%32.
+
+template <int PREC, int BM, int BN>
+struct TileSmem {
+  // FP32 operands are stored k-major ([k][row]) so that a lane's single value per MFMA is
+  // read from consecutive addresses; BF16 operands row-major ([row][k]) so a lane reads
+  // its 8 consecutive k values as one 16-byte access.
+  static constexpr int LDF_A = BM + 4, LDF_B = BN + 4;
+  static constexpr int LDH = kBK + 8;
+  static constexpr int kFp32Bytes = kBK * (LDF_A + LDF_B) * 4;
+  static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * 2;
+  static constexpr int kBytes = PREC == kFP32 ? kFp32Bytes : kBf16Bytes;
+};
+
+template <int PREC, int WGM, int WGN, int TM, int TN>
+__device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&acc)[TM][TN]) {
+  constexpr int BM = WGM * TM * 32, BN = WGN * TN * 32;
+  using S = TileSmem<PREC, BM, BN>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  if constexpr (PREC == kFP32) {
+    const float* sA = reinterpret_cast<const float*>(smem);
+    const float* sB = sA + kBK * S::LDF_A;
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 2) {
+      float a[TM], b[TN];
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+        a[tm] = sA[(kk + (lane >> 5)) * S::LDF_A + wm * TM * 32 + tm * 32 + (lane & 31)];
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn)
+        b[tn] = sB[(kk + (lane >> 5)) * S::LDF_B + wn * TN * 32 + tn * 32 + (lane & 31)];
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
+    }
+  } else {
+    const uint16_t* sAh = reinterpret_cast<const uint16_t*>(smem);
+    const uint16_t* sAl = sAh + BM * S::LDH;
+    const uint16_t* sBh = sAl + BM * S::LDH;
+    const uint16_t* sBl = sBh + BN * S::LDH;
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 16) {
+      bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
+      const int ko = kk + (lane >> 5) * 8;
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        const int r = wm * TM * 32 + tm * 32 + (lane & 31);
+        ah[tm] = *reinterpret_cast<const bf16x8_t*>(sAh + r * S::LDH + ko);
+        if constexpr (PREC == kBF16X3) al[tm] = *reinterpret_cast<const bf16x8_t*>(sAl + r * S::LDH + ko);
+      }
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const int r = wn * TN * 32 + tn * 32 + (lane & 31);
+        bh[tn] = *reinterpret_cast<const bf16x8_t*>(sBh + r * S::LDH + ko);
+        if constexpr (PREC == kBF16X3) bl[tn] = *reinterpret_cast<const bf16x8_t*>(sBl + r * S::LDH + ko);
+      }
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+          if constexpr (PREC == kBF16X3) {
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
+            acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+          }
+        }
+    }
+  }
+}
+
+// Operand loaders.  "Kmaj" sources are row-major with k contiguous (Z, X for the Gram,
+// W for W.X); the FP32 W.X B operand X is row-major with the output column contiguous.
+
+// FP32 source, k contiguous, ROWS x kBK tile -> registers (f32x4 per slot).
+template <int ROWS, int NT>
+struct F32KmajLoad {
+  static constexpr int kSlots = ROWS * kBK / 4 / NT;
+  static_assert(kSlots * NT * 4 == ROWS * kBK, "tile must split evenly");
+  f32x4 v[kSlots];
+  __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t row0, int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      v[it] = *reinterpret_cast<const f32x4*>(src + (row0 + r) * ld + k0 + c * 4);
+    }
+  }
+  // FP32 smem, k-major [k][row]
+  __device__ __forceinline__ void store_kmajor(float* s, int lds) const {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      s[(c * 4 + 0) * lds + r] = v[it].x;
+      s[(c * 4 + 1) * lds + r] = v[it].y;
+      s[(c * 4 + 2) * lds + r] = v[it].z;
+      s[(c * 4 + 3) * lds + r] = v[it].w;
+    }
+  }
+  // split to bf16 hi/lo, row-major [row][k]
+  template <bool LO>
+  __device__ __forceinline__ void store_split(uint16_t* sh, uint16_t* sl, int lds) const {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      uint16_t h0, h1, h2, h3, l0, l1, l2, l3;
+      split_bf16(v[it].x, h0, l0);
+      split_bf16(v[it].y, h1, l1);
+      split_bf16(v[it].z, h2, l2);
+      split_bf16(v[it].w, h3, l3);
+      *reinterpret_cast<u32x2*>(sh + r * lds + c * 4) = u32x2{pack2(h0, h1), pack2(h2, h3)};
+      if constexpr (LO)
+        *reinterpret_cast<u32x2*>(sl + r * lds + c * 4) = u32x2{pack2(l0, l1), pack2(l2, l3)};
+    }
+  }
+};
+
+// FP32 source with the tile's columns contiguous: kBK rows (k) x COLS -> [k][col] smem.
+template <int COLS, int NT>
+struct F32NmajLoad {
+  static constexpr int kSlots = COLS * kBK / 4 / NT;
+  static_assert(kSlots * NT * 4 == COLS * kBK, "tile must split evenly");
+  f32x4 v[kSlots];
+  __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t k0, int64_t col0) {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT, r = idx / (COLS / 4), c = idx % (COLS / 4);
+      v[it] = *reinterpret_cast<const f32x4*>(src + (k0 + r) * ld + col0 + c * 4);
+    }
+  }
+  __device__ __forceinline__ void store(float* s, int lds) const {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT, r = idx / (COLS / 4), c = idx % (COLS / 4);
+      *reinterpret_cast<f32x4*>(s + r * lds + c * 4) = v[it];
+    }
+  }
+};
+
+// BF16 source pair (hi, lo), k contiguous, ROWS x kBK tile, 16-byte vectors.
+template <int ROWS, int NT, bool LO>
+struct Bf16KmajLoad {
+  static constexpr int kSlots = (ROWS * kBK / 8 + NT - 1) / NT;
+  static constexpr int kVec = ROWS * kBK / 8;
+  u32x4 h[kSlots], l[kSlots];
+  __device__ __forceinline__ void load(const uint16_t* srch, const uint16_t* srcl, int64_t ld,
+                                       int64_t row0, int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (kVec % NT == 0 || idx < kVec) {
+        const int r = idx / (kBK / 8), c = idx % (kBK / 8);
+        const int64_t off = (row0 + r) * ld + k0 + c * 8;
+        h[it] = *reinterpret_cast<const u32x4*>(srch + off);
+        if constexpr (LO) l[it] = *reinterpret_cast<const u32x4*>(srcl + off);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint16_t* sh, uint16_t* sl, int lds) const {
+#pragma unroll
+    for (int it = 0; it < kSlots; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (kVec % NT == 0 || idx < kVec) {
+        const int r = idx / (kBK / 8), c = idx % (kBK / 8);
+        *reinterpret_cast<u32x4*>(sh + r * lds + c * 8) = h[it];
+        if constexpr (LO) *reinterpret_cast<u32x4*>(sl + r * lds + c * 8) = l[it];
+      }
+    }
+  }
+};
+
+// ----------------------------------------------------------------------------------------
+// Gram: part[s][i][j] = sum_{k in chunk s} Z[i][k] X[j][k]
+
+template <int PREC, int WGM, int WGN, int TM, int TN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
+  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
+  using S = TileSmem<PREC, BM, BN>;
+  __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
+
+  const int tile = xcd_remap(blockIdx.x, g.total);
+  const int f = find_problem(g.pre, g.np, tile);
+  const ProbDev& P = g.desc[f];
+  if (step >= P.K) return;
+  const int local = tile - g.pre[f];
+  const int tn = local % P.gram_tn;
+  const int rest = local / P.gram_tn;
+  const int tm = rest % P.gram_tm;
+  const int s = rest / P.gram_tm;
+  const int64_t kbeg = (int64_t)s * P.kchunk;
+  const int64_t kend = min(kbeg + P.kchunk, P.ldz);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+
+  f32x16_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  if constexpr (PREC == kFP32) {
+    F32KmajLoad<BM, NT> la;
+    F32KmajLoad<BN, NT> lb;
+    float* sA = reinterpret_cast<float*>(smem);
+    float* sB = sA + kBK * S::LDF_A;
+    if (kbeg < kend) {
+      la.load(P.Z, P.ldz, m0, kbeg);
+      lb.load(P.Xf, P.ldz, n0, kbeg);
+    }
+    for (int64_t kb = kbeg; kb < kend; kb += kBK) {
+      __syncthreads();
+      la.store_kmajor(sA, S::LDF_A);
+      lb.store_kmajor(sB, S::LDF_B);
+      __syncthreads();
+      if (kb + kBK < kend) {
+        la.load(P.Z, P.ldz, m0, kb + kBK);
+        lb.load(P.Xf, P.ldz, n0, kb + kBK);
+      }
+      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+    }
+  } else {
+    constexpr bool LO = PREC == kBF16X3;
+    F32KmajLoad<BM, NT> la;
+    Bf16KmajLoad<BN, NT, LO> lb;
+    uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
+    uint16_t* sAl = sAh + BM * S::LDH;
+    uint16_t* sBh = sAl + BM * S::LDH;
+    uint16_t* sBl = sBh + BN * S::LDH;
+    if (kbeg < kend) {
+      la.load(P.Z, P.ldz, m0, kbeg);
+      lb.load(P.Xh, P.Xl, P.ldz, n0, kbeg);
+    }
+    for (int64_t kb = kbeg; kb < kend; kb += kBK) {
+      __syncthreads();
+      la.template store_split<LO>(sAh, sAl, S::LDH);
+      lb.store(sBh, sBl, S::LDH);
+      __syncthreads();
+      if (kb + kBK < kend) {
+        la.load(P.Z, P.ldz, m0, kb + kBK);
+        lb.load(P.Xh, P.Xl, P.ldz, n0, kb + kBK);
+      }
+      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+    }
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* out = P.part + (int64_t)s * P.Mp_pad * P.ldn;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t i = m0 + wm * TM * 32 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int64_t j = n0 + wn * TN * 32 + b * 32 + (lane & 31);
+        out[i * P.ldn + j] = acc[a][b][r];
+      }
+}
+
+// ----------------------------------------------------------------------------------------
+// Row softmax of the logits (eq. 16), one workgroup of 256 per particle row.
+
+__device__ __forceinline__ double block_reduce_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  v = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+  return v;
+}
+
+__device__ __forceinline__ double block_reduce_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  v = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v += red[w];
+  return v;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
+  extern __shared__ double sL[];
+  __shared__ double red[8];
+  const int row = blockIdx.x;
+  const int f = find_problem(g.pre, g.np, row);
+  const ProbDev& P = g.desc[f];
+  if (step >= P.K) return;
+  const int64_t i = row - g.pre[f];
+  const double t = step_time(P, step);
+  const double alpha = 1.0 - t * (1.0 - P.eps);
+  const double inv_beta2 = 1.0 / t;
+  const int N = P.N;
+  const int64_t pstride = (int64_t)P.Mp_pad * P.ldn;
+  const float* prow = P.part + i * P.ldn;
+
+  double mx = -INFINITY;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    double gs = 0.0;
+    for (int s = 0; s < P.S; ++s) gs += (double)prow[s * pstride + j];
+    const double L = (alpha * gs - 0.5 * alpha * alpha * (double)P.xnorm[j]) * inv_beta2;
+    sL[j] = L;
+    mx = fmax(mx, L);
+  }
+  mx = block_reduce_max(mx, red);
+  double sum = 0.0;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double e = (double)expf((float)(sL[j] - mx));
+    sL[j] = e;
+    sum += e;
+  }
+  sum = block_reduce_sum(sum, red);
+  const double inv = 1.0 / sum;
+  for (int j = threadIdx.x; j < P.ldn; j += blockDim.x) {
+    const float w = j < N ? (float)(sL[j] * inv) : 0.0f;
+    if constexpr (PREC == kFP32) {
+      P.W[i * P.ldn + j] = w;
+    } else {
+      uint16_t h, l;
+      split_bf16(w, h, l);
+      P.Wh[i * P.ldn + j] = h;
+      P.Wl[i * P.ldn + j] = PREC == kBF16X3 ? l : (uint16_t)0;
+    }
+    if (P.weights_out != nullptr && j < N) P.weights_out[i * N + j] = w;
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// W.X with the fused score / noise / Euler-Maruyama epilogue.
+// Tile = BM particles x BN state components; contraction over the (padded) members.
+
+template <int PREC, int WGM, int WGN, int TM, int TN, bool SCORE>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
+                                                       unsigned long long* nonfinite) {
+  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
+  using S = TileSmem<PREC, BM, BN>;
+  constexpr int LDC = BN + 4;
+  constexpr int kEpiBytes = BM * LDC * 4;
+  constexpr int kBytes = S::kBytes > kEpiBytes ? S::kBytes : kEpiBytes;
+  __shared__ __attribute__((aligned(16))) char smem[kBytes];
+
+  const int tile = xcd_remap(blockIdx.x, g.total);
+  const int f = find_problem(g.pre, g.np, tile);
+  const ProbDev& P = g.desc[f];
+  if (!SCORE && step >= P.K) return;
+  const int local = tile - g.pre[f];
+  const int tm = local % P.wx_tm;
+  const int tn = local / P.wx_tm;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+
+  f32x16_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  const int64_t kend = P.ldn;
+  if constexpr (PREC == kFP32) {
+    F32KmajLoad<BM, NT> la;
+    F32NmajLoad<BN, NT> lb;
+    float* sA = reinterpret_cast<float*>(smem);
+    float* sB = sA + kBK * S::LDF_A;
+    la.load(P.W, P.ldn, m0, 0);
+    lb.load(P.Xf, P.ldz, 0, n0);
+    for (int64_t kb = 0; kb < kend; kb += kBK) {
+      __syncthreads();
+      la.store_kmajor(sA, S::LDF_A);
+      lb.store(sB, S::LDF_B);
+      __syncthreads();
+      if (kb + kBK < kend) {
+        la.load(P.W, P.ldn, m0, kb + kBK);
+        lb.load(P.Xf, P.ldz, kb + kBK, n0);
+      }
+      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+    }
+  } else {
+    constexpr bool LO = PREC == kBF16X3;
+    Bf16KmajLoad<BM, NT, LO> la;
+    Bf16KmajLoad<BN, NT, LO> lb;
+    uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
+    uint16_t* sAl = sAh + BM * S::LDH;
+    uint16_t* sBh = sAl + BM * S::LDH;
+    uint16_t* sBl = sBh + BN * S::LDH;
+    la.load(P.Wh, P.Wl, P.ldn, m0, 0);
+    lb.load(P.XTh, P.XTl, P.ldn, n0, 0);
+    for (int64_t kb = 0; kb < kend; kb += kBK) {
+      __syncthreads();
+      la.store(sAh, sAl, S::LDH);
+      lb.store(sBh, sBl, S::LDH);
+      __syncthreads();
+      if (kb + kBK < kend) {
+        la.load(P.Wh, P.Wl, P.ldn, m0, kb + kBK);
+        lb.load(P.XTh, P.XTl, P.ldn, n0, kb + kBK);
+      }
+      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+    }
+  }
+
+  // accumulators -> LDS, then a row-major pass with 4 consecutive components per thread
+  __syncthreads();
+  float* sC = reinterpret_cast<float*>(smem);
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * TM * 32 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * TN * 32 + b * 32 + (lane & 31);
+          sC[row * LDC + col] = acc[a][b][r];
+        }
+  }
+  __syncthreads();
+
+  const StepScalars sc = step_scalars(step_time(P, step), P.eps, P.K);
+  unsigned int bad = 0;
+  for (int q = threadIdx.x; q < BM * BN / 4; q += NT) {
+    const int r = q / (BN / 4), c4 = q % (BN / 4);
+    const int64_t i = m0 + r, e = n0 + c4 * 4;
+    if (i >= P.Mp || e >= P.d) continue;
+    const f32x4 xh = *reinterpret_cast<const f32x4*>(sC + r * LDC + c4 * 4);
+    float* zp = P.Z + i * P.ldz + e;
+    const f32x4 z = *reinterpret_cast<const f32x4*>(zp);
+    const f32x4 a = *reinterpret_cast<const f32x4*>(P.A + e);
+    const f32x4 bb = *reinterpret_cast<const f32x4*>(P.B + e);
+    f32x4 s;
+    s.x = posterior_score(z.x, xh.x, a.x, bb.x, sc, P.obs_op);
+    s.y = posterior_score(z.y, xh.y, a.y, bb.y, sc, P.obs_op);
+    s.z = posterior_score(z.z, xh.z, a.z, bb.z, sc, P.obs_op);
+    s.w = posterior_score(z.w, xh.w, a.w, bb.w, sc, P.obs_op);
+    const int64_t rem = P.d - e;  // >= 1 valid components in this quad
+    if constexpr (SCORE) {
+      float* so = P.score_out + i * P.d + e;
+      so[0] = s.x;
+      if (rem > 1) so[1] = s.y;
+      if (rem > 2) so[2] = s.z;
+      if (rem > 3) so[3] = s.w;
+    } else {
+      const f32x4 xi = normals4((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, P);
+      f32x4 zn;
+      zn.x = em_step(z.x, s.x, xi.x, sc);
+      zn.y = rem > 1 ? em_step(z.y, s.y, xi.y, sc) : 0.0f;
+      zn.z = rem > 2 ? em_step(z.z, s.z, xi.z, sc) : 0.0f;
+      zn.w = rem > 3 ? em_step(z.w, s.w, xi.w, sc) : 0.0f;
+      bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
+      *reinterpret_cast<f32x4*>(zp) = zn;
+    }
+  }
+  if (!SCORE && bad) atomicAdd(nonfinite, (unsigned long long)bad);
+}
+
+// ----------------------------------------------------------------------------------------
+// One-off kernels of an analysis
+
+__global__ void k_densify(ProbDev P, unsigned long long* bad_obs) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= P.n_obs) return;
+  const int64_t e = P.obs_idx[m];
+  if (e < 0 || e >= P.d) {
+    atomicAdd(bad_obs, 1ull);
+    return;
+  }
+  atomicAdd(P.A + e, P.obs_val[m] * P.inv_sig2);
+  atomicAdd(P.B + e, P.inv_sig2);
+}
+
+// Member row j: |x_j|^2 (FP64 accumulation) and the padded FP32 or bf16 hi/lo copy.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_prep_rows(ProbDev P) {
+  __shared__ double red[8];
+  const int64_t j = blockIdx.x;
+  const float* x = P.X + j * P.d;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < P.d; e += blockDim.x) {
+    const float v = x[e];
+    acc += (double)v * (double)v;
+    if constexpr (PREC == kFP32) {
+      P.Xf[j * P.ldz + e] = v;
+    } else {
+      uint16_t h, l;
+      split_bf16(v, h, l);
+      P.Xh[j * P.ldz + e] = h;
+      P.Xl[j * P.ldz + e] = PREC == kBF16X3 ? l : (uint16_t)0;
+    }
+  }
+  acc = block_reduce_sum(acc, red);
+  if (threadIdx.x == 0) P.xnorm[j] = (float)acc;
+}
+
+// XT[e][j] = X[j][e] over the padded N_pad x ldz block (bf16 hi and lo).
+__global__ __launch_bounds__(256) void k_transpose(ProbDev P) {
+  __shared__ uint16_t th[64][66], tl[64][66];
+  const int64_t e0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    th[r][tx] = P.Xh[(j0 + r) * P.ldz + e0 + tx];
+    tl[r][tx] = P.Xl[(j0 + r) * P.ldz + e0 + tx];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    P.XTh[(e0 + r) * P.ldn + j0 + tx] = th[tx][r];
+    P.XTl[(e0 + r) * P.ldn + j0 + tx] = tl[tx][r];
+  }
+}
+
+// Initial particles: N(0, I) at t = 1, Philox step word 0xFFFFFFFF.
+__global__ void k_init_z(ProbDev P) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  const int64_t e = q * 4;
+  if (e >= P.d) return;
+  const f32x4 n = normals4((uint32_t)q, (uint32_t)i, 0xFFFFFFFFu, P);
+  const int64_t rem = P.d - e;
+  const f32x4 v = {n.x, rem > 1 ? n.y : 0.f, rem > 2 ? n.z : 0.f, rem > 3 ? n.w : 0.f};
+  *reinterpret_cast<f32x4*>(P.Z + i * P.ldz + e) = v;
+}
+
+__global__ void k_load_z(ProbDev P) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (e < P.d) P.Z[i * P.ldz + e] = P.zin[i * P.d + e];
+}
+
+__global__ void k_store_post(ProbDev P) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (e < P.d) P.post[i * P.d + e] = P.Z[i * P.ldz + e];
+}
+
+// Spread relaxation toward the prior spread per component (ddof = 1 on both sides).
+__global__ void k_relax(ProbDev P, double r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.d) return;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < P.Mp; ++i) s += P.Z[i * P.ldz + e];
+  const double mean = s / P.Mp;
+  for (int64_t i = 0; i < P.Mp; ++i) {
+    const double v = P.Z[i * P.ldz + e] - mean;
+    s2 += v * v;
+  }
+  const double sd_post = sqrt(s2 / (P.Mp - 1));
+  double xs = 0.0, xs2 = 0.0;
+  for (int64_t j = 0; j < P.N; ++j) xs += P.X[j * P.d + e];
+  const double xmean = xs / P.N;
+  for (int64_t j = 0; j < P.N; ++j) {
+    const double v = P.X[j * P.d + e] - xmean;
+    xs2 += v * v;
+  }
+  const double sd_prior = sqrt(xs2 / (P.N - 1));
+  const double fac = sd_post > 0.0 ? 1.0 - r + r * sd_prior / sd_post : 1.0;
+  for (int64_t i = 0; i < P.Mp; ++i) {
+    float* zp = P.Z + i * P.ldz + e;
+    *zp = (float)(mean + ((double)*zp - mean) * fac);
+  }
+}
+
+__global__ void k_stats(const float* ens, int32_t n, int64_t d, float* mean, float* spread) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d) return;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += ens[i * d + e];
+  const double m = s / n;
+  for (int64_t i = 0; i < n; ++i) {
+    const double v = ens[i * d + e] - m;
+    s2 += v * v;
+  }
+  mean[e] = (float)m;
+  spread[e] = (float)sqrt(s2 / (n - 1));
+}
+
+__global__ void k_rng_normal(uint32_t k0, uint32_t k1, uint32_t filter, uint32_t step,
+                             uint32_t particle, int64_t n, float* out, uint32_t* raw) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q * 4 >= n) return;
+  const Words4 w = philox4x32_10((uint32_t)q, particle, step, filter, k0, k1);
+  if (raw != nullptr) {
+    raw[q * 4 + 0] = w.w0;
+    raw[q * 4 + 1] = w.w1;
+    raw[q * 4 + 2] = w.w2;
+    raw[q * 4 + 3] = w.w3;
+  }
+  float v[4];
+  box_muller(w.w0, w.w1, v[0], v[1]);
+  box_muller(w.w2, w.w3, v[2], v[3]);
+  for (int c = 0; c < 4; ++c)
+    if (q * 4 + c < n) out[q * 4 + c] = v[c];
+}
+
+// ----------------------------------------------------------------------------------------
+// host launchers
+
+namespace {
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+}
+
+#define ENSF_GRAM_CASE(PR, C, WGM, WGN, TM, TN)                                          \
+  if (prec == PR && cfg == C) {                                                          \
+    hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN>), dim3(g.total), dim3(64 * WGM * WGN), \
+                       0, s, g, step);                                                   \
+    return hipGetLastError();                                                            \
+  }
+
+hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipStream_t s) {
+  if (g.total <= 0) return hipSuccess;
+  ENSF_GRAM_CASE(kFP32, kGram128, 2, 2, 2, 2)
+  ENSF_GRAM_CASE(kFP32, kGram64, 2, 2, 1, 1)
+  ENSF_GRAM_CASE(kFP32, kGram32, 1, 1, 1, 1)
+  ENSF_GRAM_CASE(kBF16X3, kGram128, 2, 2, 2, 2)
+  ENSF_GRAM_CASE(kBF16X3, kGram64, 2, 2, 1, 1)
+  ENSF_GRAM_CASE(kBF16X3, kGram32, 1, 1, 1, 1)
+  ENSF_GRAM_CASE(kBF16, kGram128, 2, 2, 2, 2)
+  ENSF_GRAM_CASE(kBF16, kGram64, 2, 2, 1, 1)
+  ENSF_GRAM_CASE(kBF16, kGram32, 1, 1, 1, 1)
+  return hipErrorInvalidValue;
+}
+
+#define ENSF_WX_CASE(PR, C, WGM, WGN, TM, TN)                                                \
+  if (prec == PR && cfg == C) {                                                              \
+    if (score_mode)                                                                          \
+      hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, true>), dim3(g.total),                  \
+                         dim3(64 * WGM * WGN), 0, s, g, step, nonfinite);                    \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, false>), dim3(g.total),                 \
+                         dim3(64 * WGM * WGN), 0, s, g, step, nonfinite);                    \
+    return hipGetLastError();                                                                \
+  }
+
+hipError_t launch_wx(int prec, int cfg, bool score_mode, const GroupedLaunch& g, int step,
+                     unsigned long long* nonfinite, hipStream_t s) {
+  if (g.total <= 0) return hipSuccess;
+  ENSF_WX_CASE(kFP32, kWx128, 2, 2, 2, 2)
+  ENSF_WX_CASE(kFP32, kWx64, 2, 2, 1, 2)
+  ENSF_WX_CASE(kFP32, kWx32, 1, 2, 1, 2)
+  ENSF_WX_CASE(kBF16X3, kWx128, 2, 2, 2, 2)
+  ENSF_WX_CASE(kBF16X3, kWx64, 2, 2, 1, 2)
+  ENSF_WX_CASE(kBF16X3, kWx32, 1, 2, 1, 2)
+  ENSF_WX_CASE(kBF16, kWx128, 2, 2, 2, 2)
+  ENSF_WX_CASE(kBF16, kWx64, 2, 2, 1, 2)
+  ENSF_WX_CASE(kBF16, kWx32, 1, 2, 1, 2)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ldn, hipStream_t s) {
+  if (g.total <= 0) return hipSuccess;
+  const size_t shm = (size_t)max_ldn * sizeof(double);
+  if (prec == kFP32) {
+    hipLaunchKernelGGL(k_softmax<kFP32>, dim3(g.total), dim3(256), shm, s, g, step);
+  } else if (prec == kBF16X3) {
+    hipLaunchKernelGGL(k_softmax<kBF16X3>, dim3(g.total), dim3(256), shm, s, g, step);
+  } else {
+    hipLaunchKernelGGL(k_softmax<kBF16>, dim3(g.total), dim3(256), shm, s, g, step);
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_softmax_smem_limit(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_softmax<kFP32>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_softmax<kBF16X3>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_softmax<kBF16>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s) {
+  if (p.n_obs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_densify, dim3(blocks_for(p.n_obs, 256)), dim3(256), 0, s, p, bad_obs);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s) {
+  if (prec == kFP32)
+    hipLaunchKernelGGL(k_prep_rows<kFP32>, dim3(p.N), dim3(256), 0, s, p);
+  else if (prec == kBF16X3)
+    hipLaunchKernelGGL(k_prep_rows<kBF16X3>, dim3(p.N), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL(k_prep_rows<kBF16>, dim3(p.N), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const ProbDev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)(p.ldz / 64), (unsigned)(p.N_pad / 64)),
+                     dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_z(const ProbDev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_z, dim3(blocks_for((p.d + 3) / 4, 256), (unsigned)p.Mp), dim3(256),
+                     0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_z(const ProbDev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_load_z, dim3(blocks_for(p.d, 256), (unsigned)p.Mp), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_post(const ProbDev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_post, dim3(blocks_for(p.d, 256), (unsigned)p.Mp), dim3(256), 0, s,
+                     p);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax(const ProbDev& p, double r, hipStream_t s) {
+  hipLaunchKernelGGL(k_relax, dim3(blocks_for(p.d, 256)), dim3(256), 0, s, p, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_normal(uint64_t seed, uint32_t filter, uint32_t step, uint32_t particle,
+                             int64_t n, float* out, uint32_t* raw, hipStream_t s) {
+  const int64_t nq = (n + 3) / 4;
+  hipLaunchKernelGGL(k_rng_normal, dim3(blocks_for(nq, 256)), dim3(256), 0, s,
+                     (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), filter, step,
+                     particle, n, out, raw);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const float* ens, int32_t n, int64_t d, float* mean, float* spread,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(blocks_for(d, 256)), dim3(256), 0, s, ens, n, d, mean, spread);
+  return hipGetLastError();
+}
+
+}  // namespace ensf
