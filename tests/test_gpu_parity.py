@@ -217,3 +217,66 @@ def test_out_of_range_observation_and_nonfinite_reported(dev):
         ensf.ensf_analysis(ctx.handle, X, post, idx[:1], val[:1], 1.0, 10, 1)
         st, n = ensf.ensf_sync_status(ctx.handle)
         assert st == ensf.ENSF_ENONFINITE and n > 0
+
+
+# ---------------------------------------------------------------------------------------
+# Gaussian prior, linear observation, large ensemble: the GPU particles must follow the
+# closed-form recursion of the scheme (and the Kalman gap is reported)
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_linear_gaussian_large_ensemble(dev, precision):
+    from oracle import linear_gaussian as lg
+    N, M, K, sig, y = 16384, 4096, 200, 1.0, 1.0
+    rng = np.random.default_rng(21)
+    X = (0.3 + rng.standard_normal((N, 2))).astype(np.float32)
+    p = workloads.Problem(X=X, truth=None, obs_idx=np.array([0], np.int32),
+                          obs_val=np.array([y], np.float32), sigma_o=sig, n_steps=K, seed=9,
+                          obs_op="linear")
+    Z = _run(dev, p, precision, n_particles=M, obs_op="linear")
+    Xd = X.astype(np.float64)
+    for e, (A, B) in enumerate([(y / sig ** 2, 1 / sig ** 2), (0.0, 0.0)]):
+        m, v = lg.em_recursion(Xd[:, e].mean(), Xd[:, e].var(ddof=1), A, B, K)
+        km, kv = (lg.kalman(Xd[:, e].mean(), Xd[:, e].var(ddof=1), y, sig ** 2) if B
+                  else (Xd[:, e].mean(), Xd[:, e].var(ddof=1)))
+        print(f"{precision} e{e}: mean {Z[:, e].mean():.4f} recursion {m:.4f} Kalman {km:.4f}; "
+              f"var {Z[:, e].var(ddof=1):.4f} recursion {v:.4f} Kalman {kv:.4f}")
+        assert abs(Z[:, e].mean() - m) < 4 * np.sqrt(v / M) + 0.02
+        assert abs(Z[:, e].var(ddof=1) / v - 1) < 4 * np.sqrt(2.0 / M) + 0.05
+
+
+def test_no_observations_and_linear_operator_match_oracle(dev):
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((9, 300)).astype(np.float32)
+    empty = np.zeros(0, np.int32)
+    p = workloads.Problem(X=X, truth=None, obs_idx=empty, obs_val=np.zeros(0, np.float32),
+                          sigma_o=1.0, n_steps=40, seed=4)
+    got = _run(dev, p, "fp32", n_particles=6)
+    want = O.analysis(X, empty, np.zeros(0), 1.0, 40, seed=4, n_particles=6)
+    assert np.abs(got - want).max() <= 5e-4 * np.abs(want).max()
+    idx = np.arange(0, 300, 2).astype(np.int32)
+    y = rng.standard_normal(idx.size).astype(np.float32)
+    p = workloads.Problem(X=X, truth=None, obs_idx=idx, obs_val=y, sigma_o=0.7, n_steps=40,
+                          seed=4, obs_op="linear")
+    got = _run(dev, p, "fp32", n_particles=6, obs_op="linear")
+    want = O.analysis(X, idx, y, 0.7, 40, seed=4, obs_op="linear", n_particles=6)
+    assert np.abs(got - want).max() <= 5e-4 * np.abs(want).max()
+
+
+def test_ensemble_stats_and_spread_relaxation(dev):
+    rng = np.random.default_rng(3)
+    E = rng.standard_normal((37, 999)).astype(np.float32)
+    mean = torch.empty(999, device=dev)
+    sd = torch.empty(999, device=dev)
+    ensf.ensf_ensemble_stats(_gpu(E, dev), mean, sd)
+    torch.cuda.synchronize()
+    m, s = O.posterior_stats(E.astype(np.float64))
+    np.testing.assert_allclose(mean.cpu().numpy(), m, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(sd.cpu().numpy(), s, rtol=1e-5, atol=1e-6)
+    X = (2.0 * rng.standard_normal((12, 256))).astype(np.float32)
+    p = workloads.Problem(X=X, truth=None, obs_idx=np.arange(256, dtype=np.int32),
+                          obs_val=np.zeros(256, np.float32), sigma_o=0.5, n_steps=30, seed=6)
+    got = _run(dev, p, "fp32", spread_relax=1.0)
+    want = O.analysis(X, p.obs_idx, p.obs_val, 0.5, 30, seed=6, spread_relax=1.0)
+    np.testing.assert_allclose(got.std(0, ddof=1), X.astype(np.float64).std(0, ddof=1),
+                               rtol=1e-4)
+    assert np.abs(got - want).max() <= 1e-3 * np.abs(want).max()
