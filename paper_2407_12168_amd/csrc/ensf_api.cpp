@@ -128,8 +128,8 @@ ensf_status validate(const ensf_problem& p) {
 TileChoice heuristic_tiles(int64_t n, int64_t mp) {
   TileChoice c;
   const int64_t mn = std::min(n, mp);
-  c.gram = mn >= 128 ? kGram128 : mn >= 48 ? kGram64 : kGram32;
-  c.wx = mp >= 128 ? kWx128 : mp >= 48 ? kWx64 : kWx32;
+  c.gram = mn >= 768 ? kGram256 : mn >= 128 ? kGram128 : mn >= 48 ? kGram64 : kGram32;
+  c.wx = mp >= 768 ? kWx256 : mp >= 128 ? kWx128 : mp >= 48 ? kWx64 : kWx32;
   return c;
 }
 
@@ -159,12 +159,12 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.obs_op = obs_op;
   P.eps = eps;
   P.t_score = 1.0;
-  P.Mp_pad = (int32_t)round_up(P.Mp, kRowPad);
-  P.N_pad = (int32_t)round_up(P.N, kRowPad);
-  P.ldn = P.N_pad;
-  P.ldz = round_up(P.d, kColPad);
-
   const int bm = gram_bm(tc.gram), bn = gram_bn(tc.gram);
+  P.Mp_pad = (int32_t)round_up(P.Mp, std::max({bm, wx_bp(tc.wx), 64}));
+  P.N_pad = (int32_t)round_up(P.N, std::max(bn, 64));
+  P.ldn = P.N_pad;
+  P.ldz = round_up(P.d, std::max(wx_be(tc.wx), 128));
+
   P.gram_tm = (int32_t)ceil_div(P.Mp, bm);
   P.gram_tn = (int32_t)ceil_div(P.N, bn);
   const int64_t tiles = (int64_t)P.gram_tm * P.gram_tn;
@@ -177,8 +177,8 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   s = std::min<int64_t>(s, P.ldz / kBK);
   P.kchunk = round_up(ceil_div(P.ldz, s), kBK);
   P.S = (int32_t)ceil_div(P.ldz, P.kchunk);
-  P.wx_tm = (int32_t)ceil_div(P.Mp, wx_bm(tc.wx));
-  P.wx_tn = (int32_t)ceil_div(P.d, wx_bn(tc.wx));
+  P.wx_tp = (int32_t)ceil_div(P.Mp, wx_bp(tc.wx));
+  P.wx_te = (int32_t)ceil_div(P.d, wx_be(tc.wx));
 
   P.Z = reinterpret_cast<float*>(take((size_t)P.Mp_pad * P.ldz * 4));
   if (prec == kFP32) {
@@ -266,7 +266,7 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
     off = layout_problem(P, probs[f], prec, plan.tiles, c->opt.obs_op, c->opt.eps_alpha, off,
                          nullptr);
     const int64_t g = (int64_t)P.gram_tm * P.gram_tn * P.S;
-    const int64_t w = (int64_t)P.wx_tm * P.wx_tn;
+    const int64_t w = (int64_t)P.wx_tp * P.wx_te;
     if (plan.pre_gram[f] + g > INT32_MAX || plan.pre_wx[f] + w > INT32_MAX) return ENSF_EINVAL;
     plan.pre_gram[f + 1] = plan.pre_gram[f] + (int32_t)g;
     plan.pre_rows[f + 1] = plan.pre_rows[f] + P.Mp;

@@ -8,11 +8,9 @@ namespace ensf {
 enum Prec : int { kFP32 = 0, kBF16X3 = 1, kBF16 = 2 };
 enum ObsOp : int { kArctan = 0, kLinear = 1 };
 
-// Row and column paddings of every workspace matrix: rows of the particle and member
-// dimensions are padded to kRowPad, the state dimension to kColPad.  All tile shapes
-// divide these, so kernels never read outside the allocation, and the padding is zero.
-constexpr int kRowPad = 128;
-constexpr int kColPad = 128;
+// Rows of the particle and member dimensions and the state dimension of every workspace
+// matrix are padded to multiples of the chosen tile shapes (at least 64 and 128), so
+// kernels never read outside an allocation; the padding is zero.
 constexpr int kMaxMembers = 16384;
 
 // One analysis problem as the kernels see it (device-resident table, one entry per
@@ -47,7 +45,7 @@ struct ProbDev {
   int32_t obs_op;
   double eps, t_score;
   int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
-  int32_t wx_tm, wx_tn;       // W.X tiles along particles, elements
+  int32_t wx_tp, wx_te;       // W.X tiles along particles, state components
 };
 
 // Per-step scalars in FP32, computed in FP64 from (t, eps) exactly as the oracle does.
@@ -64,13 +62,18 @@ struct GroupedLaunch {
 };
 
 // Kernel-shape identifiers chosen by the host (heuristic or autotuner).
-enum GramCfg : int { kGram128 = 0, kGram64 = 1, kGram32 = 2, kNumGram = 3 };
-enum WxCfg : int { kWx128 = 0, kWx64 = 1, kWx32 = 2, kNumWx = 3 };
+// Gram tiles: particles x members.
+enum GramCfg : int { kGram128 = 0, kGram64 = 1, kGram32 = 2, kGram256 = 3, kNumGram = 4 };
+// W.X tiles: state components x particles.
+enum WxCfg : int { kWx128 = 0, kWx64 = 1, kWx32 = 2, kWx256 = 3, kWx128x256 = 4, kNumWx = 5 };
 
-inline int gram_bm(int c) { return c == kGram128 ? 128 : c == kGram64 ? 64 : 32; }
-inline int gram_bn(int c) { return gram_bm(c); }
-inline int wx_bm(int c) { return c == kWx128 ? 128 : c == kWx64 ? 64 : 32; }
-inline int wx_bn(int c) { return 128; }
+// kGram256 is 256 particles x 128 members; kWx256 is 256 components x 128 particles.
+inline int gram_bm(int c) { return c == kGram256 ? 256 : c == kGram128 ? 128 : c == kGram64 ? 64 : 32; }
+inline int gram_bn(int c) { return c == kGram256 ? 128 : gram_bm(c); }
+inline int wx_be(int c) { return c == kWx256 ? 256 : 128; }
+inline int wx_bp(int c) {
+  return c == kWx128x256 ? 256 : c == kWx128 || c == kWx256 ? 128 : c == kWx64 ? 64 : 32;
+}
 constexpr int kBK = 32;
 
 // Host-callable launchers (ensf_kernels.hip).

@@ -97,13 +97,14 @@ __device__ __forceinline__ float u24(uint32_t r) {
   return ((float)(r >> 8) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24, exact
 }
 
-// Box-Muller (1958): one pair of standard normals from two uniforms.
+// Box-Muller (1958): one pair of standard normals from two uniforms.  The radius uses the
+// hardware base-2 logarithm (ln u = ln 2 * log2 u) and square root; the angle 2 pi u is
+// passed in revolutions to the hardware sine and cosine, which take revolutions.
 __device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float& n0, float& n1) {
-  const float rad = sqrtf(-2.0f * logf(u24(ra)));
-  float s, c;
-  sincospif(2.0f * u24(rb), &s, &c);
-  n0 = rad * c;
-  n1 = rad * s;
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u24(ra)));
+  const float rev = u24(rb);
+  n0 = rad * __builtin_amdgcn_cosf(rev);
+  n1 = rad * __builtin_amdgcn_sinf(rev);
 }
 
 __device__ __forceinline__ f32x4 normals4(uint32_t quad, uint32_t particle, uint32_t step,
@@ -132,7 +133,8 @@ __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
 __device__ __forceinline__ float posterior_score(float z, float xh, float a, float b,
                                                  const StepScalars& sc, int op) {
   const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
-  const float lik = (op == kArctan) ? (a - b * atanf(z)) / (1.0f + z * z) : (a - b * z);
+  const float lik = (op == kArctan) ? (a - b * atanf(z)) * __builtin_amdgcn_rcpf(1.0f + z * z)
+                                    : (a - b * z);
   return prior + sc.h * lik;
 }
 
@@ -408,7 +410,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
 }
 
 // ----------------------------------------------------------------------------------------
-// Row softmax of the logits (eq. 16), one workgroup of 256 per particle row.
+// Row softmax of the logits (eq. 16), one workgroup of 256 per particle row.  The split-K
+// partials are summed in FP64 in a fixed order (deterministic): thread groups take
+// disjoint, strided sets of splits with float4 loads, and the groups are then added in
+// group order.
 
 __device__ __forceinline__ double block_reduce_max(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -434,7 +439,8 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* red) {
 
 template <int PREC>
 __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
-  extern __shared__ double sL[];
+  extern __shared__ double sL[];            // ldn logits of the row
+  __shared__ double sG[256 * 4];            // per-group partial sums (4 components each)
   __shared__ double red[8];
   const int row = blockIdx.x;
   const int f = find_problem(g.pre, g.np, row);
@@ -445,27 +451,58 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
   const double alpha = 1.0 - t * (1.0 - P.eps);
   const double inv_beta2 = 1.0 / t;
   const int N = P.N;
+  const int S = P.S;
+  const int nq = P.ldn >> 2;                 // quads of the padded row
   const int64_t pstride = (int64_t)P.Mp_pad * P.ldn;
   const float* prow = P.part + i * P.ldn;
+  const int tid = threadIdx.x;
+
+  if (nq >= 256) {
+    for (int q = tid; q < nq; q += 256) {
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      for (int s = 0; s < S; ++s) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(prow + s * pstride + 4 * q);
+        a0 += v.x; a1 += v.y; a2 += v.z; a3 += v.w;
+      }
+      sL[4 * q + 0] = a0; sL[4 * q + 1] = a1; sL[4 * q + 2] = a2; sL[4 * q + 3] = a3;
+    }
+  } else {
+    const int G = 256 / nq;                  // split groups
+    const int grp = tid / nq, q = tid % nq;
+    if (grp < G) {
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      for (int s = grp; s < S; s += G) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(prow + s * pstride + 4 * q);
+        a0 += v.x; a1 += v.y; a2 += v.z; a3 += v.w;
+      }
+      double* o = sG + 4 * (grp * nq + q);
+      o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
+    }
+    __syncthreads();
+    for (int j = tid; j < 4 * nq; j += 256) {
+      double a = 0;
+      for (int gg = 0; gg < G; ++gg) a += sG[4 * gg * nq + j];
+      sL[j] = a;
+    }
+  }
+  __syncthreads();
 
   double mx = -INFINITY;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    double gs = 0.0;
-    for (int s = 0; s < P.S; ++s) gs += (double)prow[s * pstride + j];
-    const double L = (alpha * gs - 0.5 * alpha * alpha * (double)P.xnorm[j]) * inv_beta2;
+  for (int j = tid; j < N; j += 256) {
+    const double L = (alpha * sL[j] - 0.5 * alpha * alpha * (double)P.xnorm[j]) * inv_beta2;
     sL[j] = L;
     mx = fmax(mx, L);
   }
   mx = block_reduce_max(mx, red);
   double sum = 0.0;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+  for (int j = tid; j < N; j += 256) {
     const double e = (double)expf((float)(sL[j] - mx));
     sL[j] = e;
     sum += e;
   }
   sum = block_reduce_sum(sum, red);
   const double inv = 1.0 / sum;
-  for (int j = threadIdx.x; j < P.ldn; j += blockDim.x) {
+  for (int j = tid; j < P.ldn; j += 256) {
     const float w = j < N ? (float)(sL[j] * inv) : 0.0f;
     if constexpr (PREC == kFP32) {
       P.W[i * P.ldn + j] = w;
@@ -481,26 +518,26 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
 
 // ----------------------------------------------------------------------------------------
 // W.X with the fused score / noise / Euler-Maruyama epilogue.
-// Tile = BM particles x BN state components; contraction over the (padded) members.
+// The tile computes xhat^T: BE state components (MFMA rows) x BP particles (MFMA columns),
+// contraction over the padded members.  In this orientation register group r/4 of a lane
+// holds four consecutive components of one particle, i.e. exactly the four normals of one
+// Philox counter, so the epilogue runs from the accumulators without any exchange.
 
 template <int PREC, int WGM, int WGN, int TM, int TN, bool SCORE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
-  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
-  using S = TileSmem<PREC, BM, BN>;
-  constexpr int LDC = BN + 4;
-  constexpr int kEpiBytes = BM * LDC * 4;
-  constexpr int kBytes = S::kBytes > kEpiBytes ? S::kBytes : kEpiBytes;
-  __shared__ __attribute__((aligned(16))) char smem[kBytes];
+  constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
+  using S = TileSmem<PREC, BE, BP>;
+  __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
   const int f = find_problem(g.pre, g.np, tile);
   const ProbDev& P = g.desc[f];
   if (!SCORE && step >= P.K) return;
   const int local = tile - g.pre[f];
-  const int tm = local % P.wx_tm;
-  const int tn = local / P.wx_tm;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tp = local % P.wx_tp;           // particle tile (fastest: tiles sharing X are adjacent)
+  const int te = local / P.wx_tp;
+  const int64_t e0 = (int64_t)te * BE, i0 = (int64_t)tp * BP;
 
   f32x16_t acc[TM][TN];
 #pragma unroll
@@ -512,97 +549,88 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 
   const int64_t kend = P.ldn;
   if constexpr (PREC == kFP32) {
-    F32KmajLoad<BM, NT> la;
-    F32NmajLoad<BN, NT> lb;
+    F32NmajLoad<BE, NT> la;   // X rows (members) x components, components contiguous
+    F32KmajLoad<BP, NT> lb;   // W particles x members, members contiguous
     float* sA = reinterpret_cast<float*>(smem);
     float* sB = sA + kBK * S::LDF_A;
-    la.load(P.W, P.ldn, m0, 0);
-    lb.load(P.Xf, P.ldz, 0, n0);
+    la.load(P.Xf, P.ldz, 0, e0);
+    lb.load(P.W, P.ldn, i0, 0);
     for (int64_t kb = 0; kb < kend; kb += kBK) {
       __syncthreads();
-      la.store_kmajor(sA, S::LDF_A);
-      lb.store(sB, S::LDF_B);
+      la.store(sA, S::LDF_A);
+      lb.store_kmajor(sB, S::LDF_B);
       __syncthreads();
       if (kb + kBK < kend) {
-        la.load(P.W, P.ldn, m0, kb + kBK);
-        lb.load(P.Xf, P.ldz, kb + kBK, n0);
+        la.load(P.Xf, P.ldz, kb + kBK, e0);
+        lb.load(P.W, P.ldn, i0, kb + kBK);
       }
       mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
     }
   } else {
     constexpr bool LO = PREC == kBF16X3;
-    Bf16KmajLoad<BM, NT, LO> la;
-    Bf16KmajLoad<BN, NT, LO> lb;
+    Bf16KmajLoad<BE, NT, LO> la;   // X^T components x members
+    Bf16KmajLoad<BP, NT, LO> lb;   // W particles x members
     uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* sAl = sAh + BM * S::LDH;
-    uint16_t* sBh = sAl + BM * S::LDH;
-    uint16_t* sBl = sBh + BN * S::LDH;
-    la.load(P.Wh, P.Wl, P.ldn, m0, 0);
-    lb.load(P.XTh, P.XTl, P.ldn, n0, 0);
+    uint16_t* sAl = sAh + BE * S::LDH;
+    uint16_t* sBh = sAl + BE * S::LDH;
+    uint16_t* sBl = sBh + BP * S::LDH;
+    la.load(P.XTh, P.XTl, P.ldn, e0, 0);
+    lb.load(P.Wh, P.Wl, P.ldn, i0, 0);
     for (int64_t kb = 0; kb < kend; kb += kBK) {
       __syncthreads();
       la.store(sAh, sAl, S::LDH);
       lb.store(sBh, sBl, S::LDH);
       __syncthreads();
       if (kb + kBK < kend) {
-        la.load(P.Wh, P.Wl, P.ldn, m0, kb + kBK);
-        lb.load(P.XTh, P.XTl, P.ldn, n0, kb + kBK);
+        la.load(P.XTh, P.XTl, P.ldn, e0, kb + kBK);
+        lb.load(P.Wh, P.Wl, P.ldn, i0, kb + kBK);
       }
       mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
     }
   }
 
-  // accumulators -> LDS, then a row-major pass with 4 consecutive components per thread
-  __syncthreads();
-  float* sC = reinterpret_cast<float*>(smem);
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / WGN, wn = wave % WGN;
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-      for (int b = 0; b < TN; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wm * TM * 32 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * TN * 32 + b * 32 + (lane & 31);
-          sC[row * LDC + col] = acc[a][b][r];
-        }
-  }
-  __syncthreads();
-
   const StepScalars sc = step_scalars(step_time(P, step), P.eps, P.K);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
   unsigned int bad = 0;
-  for (int q = threadIdx.x; q < BM * BN / 4; q += NT) {
-    const int r = q / (BN / 4), c4 = q % (BN / 4);
-    const int64_t i = m0 + r, e = n0 + c4 * 4;
-    if (i >= P.Mp || e >= P.d) continue;
-    const f32x4 xh = *reinterpret_cast<const f32x4*>(sC + r * LDC + c4 * 4);
-    float* zp = P.Z + i * P.ldz + e;
-    const f32x4 z = *reinterpret_cast<const f32x4*>(zp);
-    const f32x4 a = *reinterpret_cast<const f32x4*>(P.A + e);
-    const f32x4 bb = *reinterpret_cast<const f32x4*>(P.B + e);
-    f32x4 s;
-    s.x = posterior_score(z.x, xh.x, a.x, bb.x, sc, P.obs_op);
-    s.y = posterior_score(z.y, xh.y, a.y, bb.y, sc, P.obs_op);
-    s.z = posterior_score(z.z, xh.z, a.z, bb.z, sc, P.obs_op);
-    s.w = posterior_score(z.w, xh.w, a.w, bb.w, sc, P.obs_op);
-    const int64_t rem = P.d - e;  // >= 1 valid components in this quad
-    if constexpr (SCORE) {
-      float* so = P.score_out + i * P.d + e;
-      so[0] = s.x;
-      if (rem > 1) so[1] = s.y;
-      if (rem > 2) so[2] = s.z;
-      if (rem > 3) so[3] = s.w;
-    } else {
-      const f32x4 xi = normals4((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, P);
-      f32x4 zn;
-      zn.x = em_step(z.x, s.x, xi.x, sc);
-      zn.y = rem > 1 ? em_step(z.y, s.y, xi.y, sc) : 0.0f;
-      zn.z = rem > 2 ? em_step(z.z, s.z, xi.z, sc) : 0.0f;
-      zn.w = rem > 3 ? em_step(z.w, s.w, xi.w, sc) : 0.0f;
-      bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
-      *reinterpret_cast<f32x4*>(zp) = zn;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) {
+    const int64_t i = i0 + wn * TN * 32 + b * 32 + (lane & 31);
+    if (i >= P.Mp) continue;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const int64_t e = e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+        if (e >= P.d) continue;
+        const float xh0 = acc[a][b][gq * 4 + 0], xh1 = acc[a][b][gq * 4 + 1];
+        const float xh2 = acc[a][b][gq * 4 + 2], xh3 = acc[a][b][gq * 4 + 3];
+        float* zp = P.Z + i * P.ldz + e;
+        const f32x4 z = *reinterpret_cast<const f32x4*>(zp);
+        const f32x4 av = *reinterpret_cast<const f32x4*>(P.A + e);
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(P.B + e);
+        const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, P.obs_op);
+        const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, P.obs_op);
+        const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, P.obs_op);
+        const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, P.obs_op);
+        const int64_t rem = P.d - e;
+        if constexpr (SCORE) {
+          float* so = P.score_out + i * P.d + e;
+          so[0] = s0;
+          if (rem > 1) so[1] = s1;
+          if (rem > 2) so[2] = s2;
+          if (rem > 3) so[3] = s3;
+        } else {
+          const f32x4 xi = normals4((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, P);
+          f32x4 zn;
+          zn.x = em_step(z.x, s0, xi.x, sc);
+          zn.y = rem > 1 ? em_step(z.y, s1, xi.y, sc) : 0.0f;
+          zn.z = rem > 2 ? em_step(z.z, s2, xi.z, sc) : 0.0f;
+          zn.w = rem > 3 ? em_step(z.w, s3, xi.w, sc) : 0.0f;
+          bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
+          *reinterpret_cast<f32x4*>(zp) = zn;
+        }
+      }
     }
   }
   if (!SCORE && bad) atomicAdd(nonfinite, (unsigned long long)bad);
@@ -759,17 +787,17 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
     return hipGetLastError();                                                            \
   }
 
+#define ENSF_GRAM_ALL(PR)                 \
+  ENSF_GRAM_CASE(PR, kGram128, 2, 2, 2, 2) \
+  ENSF_GRAM_CASE(PR, kGram64, 2, 2, 1, 1)  \
+  ENSF_GRAM_CASE(PR, kGram32, 1, 1, 1, 1)  \
+  ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)
+
 hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
-  ENSF_GRAM_CASE(kFP32, kGram128, 2, 2, 2, 2)
-  ENSF_GRAM_CASE(kFP32, kGram64, 2, 2, 1, 1)
-  ENSF_GRAM_CASE(kFP32, kGram32, 1, 1, 1, 1)
-  ENSF_GRAM_CASE(kBF16X3, kGram128, 2, 2, 2, 2)
-  ENSF_GRAM_CASE(kBF16X3, kGram64, 2, 2, 1, 1)
-  ENSF_GRAM_CASE(kBF16X3, kGram32, 1, 1, 1, 1)
-  ENSF_GRAM_CASE(kBF16, kGram128, 2, 2, 2, 2)
-  ENSF_GRAM_CASE(kBF16, kGram64, 2, 2, 1, 1)
-  ENSF_GRAM_CASE(kBF16, kGram32, 1, 1, 1, 1)
+  ENSF_GRAM_ALL(kFP32)
+  ENSF_GRAM_ALL(kBF16X3)
+  ENSF_GRAM_ALL(kBF16)
   return hipErrorInvalidValue;
 }
 
@@ -784,18 +812,20 @@ hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipS
     return hipGetLastError();                                                                \
   }
 
+// (components x particles) per config: 128x128, 128x64, 128x32, 256x128, 128x256
+#define ENSF_WX_ALL(PR)                     \
+  ENSF_WX_CASE(PR, kWx128, 2, 2, 2, 2)      \
+  ENSF_WX_CASE(PR, kWx64, 2, 2, 2, 1)       \
+  ENSF_WX_CASE(PR, kWx32, 4, 1, 1, 1)       \
+  ENSF_WX_CASE(PR, kWx256, 4, 2, 2, 2)      \
+  ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)
+
 hipError_t launch_wx(int prec, int cfg, bool score_mode, const GroupedLaunch& g, int step,
                      unsigned long long* nonfinite, hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
-  ENSF_WX_CASE(kFP32, kWx128, 2, 2, 2, 2)
-  ENSF_WX_CASE(kFP32, kWx64, 2, 2, 1, 2)
-  ENSF_WX_CASE(kFP32, kWx32, 1, 2, 1, 2)
-  ENSF_WX_CASE(kBF16X3, kWx128, 2, 2, 2, 2)
-  ENSF_WX_CASE(kBF16X3, kWx64, 2, 2, 1, 2)
-  ENSF_WX_CASE(kBF16X3, kWx32, 1, 2, 1, 2)
-  ENSF_WX_CASE(kBF16, kWx128, 2, 2, 2, 2)
-  ENSF_WX_CASE(kBF16, kWx64, 2, 2, 1, 2)
-  ENSF_WX_CASE(kBF16, kWx32, 1, 2, 1, 2)
+  ENSF_WX_ALL(kFP32)
+  ENSF_WX_ALL(kBF16X3)
+  ENSF_WX_ALL(kBF16)
   return hipErrorInvalidValue;
 }
 
