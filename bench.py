@@ -30,24 +30,37 @@ WORKLOAD = {
        "sigma_o=0.05, K=100",
     3: "EnSF analysis d=2x256x256=131072, N=M_p=1024, arctan obs of all components, "
        "sigma_o=0.02, K=200",
+    4: "64 independent EnSF filters in one batched call: d uniform in {2x64x64, 2x128x128, "
+       "2x256x256}, N=M_p uniform in 32..512, arctan obs of 10-100% of components, "
+       "sigma_o=0.05, K=100",
 }
 
 
-def run_form(p, precision, steps, warmup, dev):
+def run_form(probs, precision, steps, warmup, dev):
+    """Times ensf_analysis (one problem) or ensf_analysis_batched (several) on `probs`."""
     import torch
     from paper_2407_12168_amd import ensf
 
-    X = torch.from_numpy(p.X).to(dev)
-    post = torch.empty_like(X)
-    idx = torch.from_numpy(p.obs_idx).to(dev)
-    val = torch.from_numpy(p.obs_val).to(dev)
     stream = torch.cuda.current_stream()
+    tens, descs = [], []
+    for p in probs:
+        X = torch.from_numpy(p.X).to(dev)
+        post = torch.empty_like(X)
+        idx = torch.from_numpy(p.obs_idx).to(dev)
+        val = torch.from_numpy(p.obs_val).to(dev)
+        tens.append((X, post, idx, val))
+        descs.append(ensf.make_problem(X, post, idx, val, p.sigma_o, p.n_steps, p.seed,
+                                       p.filter_id))
     ctx = ensf.Context(precision=precision, use_graph=True)
     h = ctx.handle
 
     def one():
-        ensf.ensf_analysis(h, X, post, idx, val, p.sigma_o, p.n_steps, p.seed, p.filter_id,
-                           stream)
+        if len(probs) == 1:
+            p, (X, post, idx, val) = probs[0], tens[0]
+            ensf.ensf_analysis(h, X, post, idx, val, p.sigma_o, p.n_steps, p.seed, p.filter_id,
+                               stream)
+        else:
+            ensf.ensf_analysis_batched(h, descs, stream)
 
     for _ in range(warmup):
         one()
@@ -69,12 +82,12 @@ def run_form(p, precision, steps, warmup, dev):
     phase_ms, n_launch = ensf.ensf_phase_times(h)
     ensf.ensf_profile_phases(h, False)
     ctx.destroy()
-    return ms, [m / n_launch for m in phase_ms], post
+    return ms, [m / n_launch for m in phase_ms]
 
 
-def roofline(p, precision, phase_avg_ms):
-    # algorithmic flops per launch: Gram = 2*M_p*N*d, W.X = 2*M_p*N*d (split forms issue 3x)
-    flops = 2.0 * p.n_members * p.n_members * p.dim
+def roofline(probs, precision, phase_avg_ms):
+    # algorithmic flops per launch: Gram = sum 2*M_p*N*d, W.X the same (split forms issue 3x)
+    flops = sum(2.0 * p.n_members * p.n_members * p.dim for p in probs)
     names = ("k_gram", "k_softmax", "k_wx")
     dom = 0 if phase_avg_ms[0] >= phase_avg_ms[2] else 2
     achieved = flops / (phase_avg_ms[dom] * 1e-3) / 1e12
@@ -85,23 +98,29 @@ def roofline(p, precision, phase_avg_ms):
             "phase_avg_ms": {n: round(v, 5) for n, v in zip(names, phase_avg_ms)}}
 
 
-def cpu_baseline(p, n_sample):
+def cpu_baseline(probs, n_sample):
+    """FP64 oracle on `n_sample` particles of the first problem, scaled to the whole job
+    (cost is linear in the particle count and in each filter's N*d*K)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import ensf as oracle_ensf
 
+    p = probs[0]
     rows = np.linspace(0, p.n_members - 1, n_sample).astype(int)
     t0 = time.perf_counter()
     oracle_ensf.analysis(p.X, p.obs_idx, p.obs_val, p.sigma_o, p.n_steps, p.seed,
-                         particle_ids=rows)
+                         filter_id=p.filter_id, particle_ids=rows)
     t = time.perf_counter() - t0
-    full_t = t * p.n_members / n_sample   # cost is linear in the particle count
+    work = lambda q: float(q.n_members) * q.n_members * q.dim * q.n_steps
+    scale = sum(work(q) for q in probs) / (work(p) * n_sample / p.n_members)
+    full_t = t * scale
+    ndk = sum(q.n_members * q.dim * q.n_steps for q in probs)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": p.n_members * p.dim * p.n_steps / full_t, "unit": "member-dim updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{n_sample} of {p.n_members} particles, full K={p.n_steps}, "
-                      f"{t:.1f}s measured, scaled by {p.n_members / n_sample:.0f}"}
+    return {"value": ndk / full_t, "unit": "member-dim updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_sample} of {p.n_members} particles of filter 0 (N={p.n_members}, "
+                      f"d={p.dim}, K={p.n_steps}), {t:.1f}s measured, scaled by {scale:.0f}"}
 
 
 def main():
@@ -109,7 +128,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16x3", "bf16"))
     ap.add_argument("--other-form", default=None,
                     help="second precision reported alongside (default: the other of fp32/bf16x3)")
@@ -125,14 +144,25 @@ def main():
 
     import workloads
     dev = torch.device("cuda:0")
-    p = workloads.config_problem(a.config)
+    if a.config == 4:
+        probs = workloads.batched_problems(n_filters=64, n_steps=100, sigma_o=0.05)
+    else:
+        probs = [workloads.config_problem(a.config)]
     print(f"# workload: {WORKLOAD[a.config]}", file=sys.stderr, flush=True)
-    ms, phase, _ = run_form(p, a.precision, a.steps, a.warmup, dev)
+    ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev)
     print(f"# {a.precision}: {ms:.3f} ms per analysis", file=sys.stderr, flush=True)
     other = a.other_form or ("bf16x3" if a.precision == "fp32" else "fp32")
-    ms2, phase2, _ = run_form(p, other, max(2, a.steps // 2), 1, dev)
+    ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev)
     print(f"# {other}: {ms2:.3f} ms per analysis", file=sys.stderr, flush=True)
-    ndk = p.n_members * p.dim * p.n_steps
+    ndk = sum(p.n_members * p.dim * p.n_steps for p in probs)
+    p0 = probs[0]
+    cfg = {"workload": WORKLOAD[a.config], "precision": a.precision}
+    if len(probs) == 1:
+        cfg.update(members=p0.n_members, particles=p0.n_members, dim=p0.dim,
+                   pseudo_steps=p0.n_steps, obs=int(p0.obs_idx.size))
+    else:
+        cfg.update(filters=len(probs), total_member_dims=int(sum(p.n_members * p.dim
+                                                                  for p in probs)))
     line = {
         "metric": "EnSF member-dim updates/s (N*d*K/s)",
         "value": ndk / (ms * 1e-3),
@@ -141,16 +171,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if a.precision == "fp32" else a.precision,
         "data": "synthetic",
-        "config": {"workload": WORKLOAD[a.config], "precision": a.precision,
-                   "members": p.n_members, "particles": p.n_members, "dim": p.dim,
-                   "pseudo_steps": p.n_steps, "obs": int(p.obs_idx.size)},
-        "roofline": roofline(p, a.precision, phase),
+        "config": cfg,
+        "roofline": roofline(probs, a.precision, phase),
         "forms": {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
-                          "roofline": roofline(p, other, phase2)},
+                          "roofline": roofline(probs, other, phase2)},
                   "speedup_bf16x3_over_fp32": (ms / ms2) if a.precision == "fp32" else (ms2 / ms)},
     }
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(p, a.cpu_particles)
+        line["cpu_baseline"] = cpu_baseline(probs, a.cpu_particles)
     print(json.dumps(line), flush=True)
 
 

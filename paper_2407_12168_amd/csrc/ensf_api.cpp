@@ -102,6 +102,7 @@ struct Plan {
   std::vector<ProbDev> desc;
   std::vector<int32_t> pre_gram, pre_rows, pre_wx;
   TileChoice tiles;
+  std::vector<double> wg_target;
   int kmax = 0;
   int max_ldn = 0;
   size_t ws_needed = 0;
@@ -135,7 +136,7 @@ TileChoice heuristic_tiles(int64_t n, int64_t mp) {
 
 // Lays out one problem's workspace at offset `off` (bytes) and fills its descriptor.
 size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileChoice& tc,
-                      int obs_op, double eps, size_t off, char* base) {
+                      int obs_op, double eps, double wg_target, size_t off, char* base) {
   auto take = [&](size_t bytes) {
     off = round_up(off, kAlign);
     char* ptr = base ? base + off : nullptr;
@@ -168,9 +169,9 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.gram_tm = (int32_t)ceil_div(P.Mp, bm);
   P.gram_tn = (int32_t)ceil_div(P.N, bn);
   const int64_t tiles = (int64_t)P.gram_tm * P.gram_tn;
-  // split-K: enough workgroups to fill the device, chunks of at least 4 k-steps, and the
-  // partial sums no larger than a quarter of the Gram's operand bytes
-  int64_t s = ceil_div(1024, tiles);
+  // split-K: this problem's share of ~1024 workgroups (enough to fill the device), chunks
+  // of at least 4 k-steps, and partial sums no larger than a quarter of the operand bytes
+  int64_t s = std::max<int64_t>(1, (int64_t)std::ceil(wg_target / (double)tiles));
   s = std::min<int64_t>(s, P.ldz / (4 * kBK));
   s = std::min<int64_t>(s, std::max<int64_t>(1, (P.Mp + P.N) * P.ldz / (4 * (int64_t)P.Mp * P.N)));
   s = std::max<int64_t>(1, (int64_t)std::llround(s * tc.split_scale));
@@ -261,10 +262,16 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
   size_t off = 0;
   plan.kmax = 0;
   plan.max_ldn = 0;
+  plan.wg_target.assign(np, 1024.0);
+  double total = 0;
+  for (const auto& p : probs) total += (double)p.n_members * p.n_particles * p.dim;
+  for (int f = 0; f < np; ++f)
+    plan.wg_target[f] = std::max(8.0, 1024.0 * (double)probs[f].n_members *
+                                          probs[f].n_particles * probs[f].dim / total);
   for (int f = 0; f < np; ++f) {
     ProbDev& P = plan.desc[f];
-    off = layout_problem(P, probs[f], prec, plan.tiles, c->opt.obs_op, c->opt.eps_alpha, off,
-                         nullptr);
+    off = layout_problem(P, probs[f], prec, plan.tiles, c->opt.obs_op, c->opt.eps_alpha,
+                         plan.wg_target[f], off, nullptr);
     const int64_t g = (int64_t)P.gram_tm * P.gram_tn * P.S;
     const int64_t w = (int64_t)P.wx_tp * P.wx_te;
     if (plan.pre_gram[f] + g > INT32_MAX || plan.pre_wx[f] + w > INT32_MAX) return ENSF_EINVAL;
@@ -283,7 +290,7 @@ void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) 
   size_t off = 0;
   for (size_t f = 0; f < probs.size(); ++f)
     off = layout_problem(plan.desc[f], probs[f], c->opt.precision, plan.tiles, c->opt.obs_op,
-                         c->opt.eps_alpha, off, c->ws);
+                         c->opt.eps_alpha, plan.wg_target[f], off, c->ws);
 }
 
 struct Uploaded {

@@ -83,8 +83,10 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    // one 32x32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += 0x9E3779B9u;
@@ -624,10 +626,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
           const f32x4 xi = normals4((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, P);
           f32x4 zn;
           zn.x = em_step(z.x, s0, xi.x, sc);
-          zn.y = rem > 1 ? em_step(z.y, s1, xi.y, sc) : 0.0f;
-          zn.z = rem > 2 ? em_step(z.z, s2, xi.z, sc) : 0.0f;
-          zn.w = rem > 3 ? em_step(z.w, s3, xi.w, sc) : 0.0f;
-          bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
+          zn.y = em_step(z.y, s1, xi.y, sc);
+          zn.z = em_step(z.z, s2, xi.z, sc);
+          zn.w = em_step(z.w, s3, xi.w, sc);
+          if (rem < 4) {  // ragged tail: keep the padding at zero
+            zn.w = 0.0f;
+            if (rem < 3) zn.z = 0.0f;
+            if (rem < 2) zn.y = 0.0f;
+          }
+          if (!isfinite(zn.x + zn.y + zn.z + zn.w))
+            bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
           *reinterpret_cast<f32x4*>(zp) = zn;
         }
       }

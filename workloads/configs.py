@@ -9,7 +9,9 @@ or the identity (the paper's own twin experiment, Sec. IV-A).
 Seeds: data_seed = 2407 + config number drives numpy's PCG64 for every draw here;
 the filter's own counter-based noise uses seed = 12168 + config number.
 """
+import os
 from dataclasses import dataclass, field
+
 import numpy as np
 
 from .fields import smooth_fields
@@ -91,12 +93,16 @@ def batched_problems(n_filters=64, n_steps=100, sigma_o=0.05, data_seed=2411, se
     """Independent filters of uneven size: d uniform over `dims`, N uniform over
     n_range (inclusive), observed fraction uniform over frac_range."""
     rng = np.random.default_rng(data_seed)
-    probs = []
+    specs = []
     for f in range(n_filters):
         levels, h, w = dims[rng.integers(len(dims))]
         N = int(rng.integers(n_range[0], n_range[1] + 1))
         frac = float(rng.uniform(*frac_range))
         sub_seed = int(rng.integers(1 << 31))
-        probs.append(make_problem(levels, h, w, N, sigma_o, n_steps, sub_seed, seed,
-                                  obs_fraction=frac, filter_id=f))
-    return probs
+        specs.append((levels, h, w, N, frac, sub_seed, f))
+    # each filter has its own seed, so drawing them concurrently is deterministic
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+        return list(ex.map(lambda sp: make_problem(sp[0], sp[1], sp[2], sp[3], sigma_o, n_steps,
+                                                   sp[5], seed, obs_fraction=sp[4],
+                                                   filter_id=sp[6]), specs))

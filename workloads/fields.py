@@ -7,7 +7,12 @@ divide by the sample standard deviation.  The power spectral density then falls 
 The paper's test state is a 2-level SQG temperature field (Sec. II-B, Sec. IV-A);
 these fields stand in for it with the same shape and a turbulence-like spectrum.
 """
+import os
+
 import numpy as np
+from scipy import fft as sfft
+
+_WORKERS = 1  # callers parallelise over fields
 
 
 def _wavenumber_magnitude(h, w):
@@ -27,8 +32,8 @@ def smooth_fields(rng, count, h, w, slope=3.0):
     for s in range(0, count, chunk):
         e = min(count, s + chunk)
         white = rng.standard_normal((e - s, h, w))
-        spec = np.fft.rfft2(white) * amp
-        f = np.fft.irfft2(spec, s=(h, w))
+        spec = sfft.rfft2(white, workers=_WORKERS) * amp
+        f = sfft.irfft2(spec, s=(h, w), workers=_WORKERS)
         f -= f.mean(axis=(1, 2), keepdims=True)
         f /= f.std(axis=(1, 2), keepdims=True)
         out[s:e] = f
