@@ -10,6 +10,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libensf.so")
+# tile shapes measured by ensf_autotune on MI355X for the benchmark shapes
+DEFAULT_TUNE_CACHE = os.path.join(HERE, "tune_gfx950.json")
 
 ENSF_OK, ENSF_EINVAL, ENSF_ENOMEM, ENSF_EHIP, ENSF_ENONFINITE, ENSF_EUNSUPPORTED = range(6)
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "bf16": 2}
@@ -121,7 +123,7 @@ def ensf_default_options():
 
 
 def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=0.0,
-                use_graph=True, device=0, tune_cache=None):
+                use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE):
     o = ensf_default_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
