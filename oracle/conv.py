@@ -11,6 +11,7 @@ Layout: NCHW arrays, weights (Cout, Cin, 3, 3), bias (Cout,).
 import math
 
 import numpy as np
+from scipy.special import erf
 
 
 def _shift(a, dy, dx):
@@ -39,11 +40,11 @@ def conv3x3_backward(x, w, gout):
 
 
 def gelu(u):
-    return 0.5 * u * (1.0 + np.vectorize(math.erf)(u / math.sqrt(2.0)))
+    return 0.5 * u * (1.0 + erf(u / math.sqrt(2.0)))
 
 
 def gelu_grad(u):
-    cdf = 0.5 * (1.0 + np.vectorize(math.erf)(u / math.sqrt(2.0)))
+    cdf = 0.5 * (1.0 + erf(u / math.sqrt(2.0)))
     pdf = np.exp(-0.5 * u * u) / math.sqrt(2.0 * math.pi)
     return cdf + u * pdf
 
@@ -104,6 +105,24 @@ def adam_step(params, grads, state, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
             vh = v / (1 - beta2 ** step)
             new.append(p - lr * mh / (np.sqrt(vh) + eps))
         out.append(tuple(new))
+    return out
+
+
+def flatten(params):
+    """Parameters in the order layer by layer, weight (Cout, Cin, 3, 3) then bias."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params])
+
+
+def unflatten(flat, c0=2, width=64, layers=6):
+    chans = [c0] + [width] * (layers - 1) + [c0]
+    out, k = [], 0
+    for i in range(layers):
+        cin, cout = chans[i], chans[i + 1]
+        w = np.asarray(flat[k:k + cout * cin * 9], dtype=np.float64).reshape(cout, cin, 3, 3)
+        k += cout * cin * 9
+        b = np.asarray(flat[k:k + cout], dtype=np.float64)
+        k += cout
+        out.append((w, b))
     return out
 
 

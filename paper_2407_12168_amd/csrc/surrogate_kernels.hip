@@ -1,0 +1,423 @@
+// HIP kernels of the convolutional forecast surrogate (gfx950).
+//
+// Activations are NHWC bf16 with the channel count padded to CP in {32, 64} (padding is
+// zero and stays zero: padded weights and biases are zero).  A 3x3 convolution with
+// periodic padding is an implicit GEMM: M = pixels, N = output channels, K = 9 taps x
+// input channels.  One workgroup (4 waves) owns one image and a band of output rows; it
+// keeps all weights and a ring of three input rows (with a one-pixel periodic halo) in
+// LDS, so each new output row costs one new input row from memory.  Wave w computes
+// 32-pixel groups w, w+4, ... of the row against all output channels with
+// v_mfma_f32_32x32x16_bf16 (FP32 accumulation).
+//
+// The input-gradient convolution is the same kernel run on the output gradient with the
+// taps flipped and the weight matrix transposed.  The weight gradient contracts over
+// pixels, which are strided in NHWC, so it stages FP32 tiles k-major in LDS and uses
+// v_mfma_f32_32x32x2_f32; per-chunk partials are reduced in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "surrogate_internal.h"
+
+namespace ensf {
+namespace sg {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+__device__ __forceinline__ float gelu(float u) {
+  return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float u) {
+  const float cdf = 0.5f * (1.0f + erff(u * 0.70710678118654752f));
+  const float pdf = 0.3989422804014327f * expf(-0.5f * u * u);
+  return cdf + u * pdf;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+// NCHW float32 (c0 channels) -> NHWC bf16 with CP channels (zero padded).
+__global__ void k_pack_input(const float* __restrict__ x, uint16_t* __restrict__ a, int batch,
+                             int c0, int H, int W, int CP) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)batch * H * W;
+  if (p >= npix) return;
+  const int64_t b = p / ((int64_t)H * W), yx = p % ((int64_t)H * W);
+  uint16_t* dst = a + p * CP;
+  for (int c = 0; c < CP; ++c)
+    dst[c] = c < c0 ? to_bf16(x[(b * c0 + c) * (int64_t)H * W + yx]) : (uint16_t)0;
+}
+
+// ---------------------------------------------------------------------------------------
+// implicit-GEMM convolution with fused epilogues
+
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  constexpr int LDW = 9 * CIN + 8;        // weight row (one output channel), bf16
+  constexpr int LDI = CIN + 8;            // one halo pixel, bf16
+  constexpr int TN = COUT / 32;
+  const int H = args.H, W = args.W;
+  uint16_t* sW = reinterpret_cast<uint16_t*>(smem_raw);
+  uint16_t* sIn = sW + COUT * LDW;
+  const int64_t row_elems = (int64_t)(W + 2) * LDI;
+  __shared__ float red[4];
+
+  const int b = blockIdx.y;
+  const int y0 = blockIdx.x * args.rows;
+  const int y1 = min(y0 + args.rows, H);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint16_t* in = args.in + (int64_t)b * H * W * CIN;
+
+  // all weights -> LDS
+  for (int v = tid; v < COUT * 9 * CIN / 8; v += 256) {
+    const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
+    *reinterpret_cast<u32x4*>(sW + co * LDW + k8 * 8) =
+        *reinterpret_cast<const u32x4*>(args.wk + (int64_t)co * 9 * CIN + k8 * 8);
+  }
+  auto load_row = [&](int yy) {  // unwrapped row index -> ring slot yy mod 3
+    const int slot = wrap(yy, 3);
+    const uint16_t* src = in + (int64_t)wrap(yy, H) * W * CIN;
+    uint16_t* dst = sIn + slot * row_elems;
+    for (int v = tid; v < (W + 2) * (CIN / 8); v += 256) {
+      const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
+      const int xs = wrap(xh - 1, W);
+      *reinterpret_cast<u32x4*>(dst + xh * LDI + c8 * 8) =
+          *reinterpret_cast<const u32x4*>(src + (int64_t)xs * CIN + c8 * 8);
+    }
+  };
+  load_row(y0 - 1);
+  load_row(y0);
+  load_row(y0 + 1);
+  __syncthreads();
+
+  float loss_local = 0.0f;
+  for (int y = y0; y < y1; ++y) {
+    for (int g = wave; g < W / 32; g += 4) {
+      f32x16_t acc[TN];
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[tn][r] = 0.0f;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const uint16_t* rowp = sIn + wrap(y + dy, 3) * row_elems +
+                               (int64_t)(32 * g + (lane & 31) + dx + 1) * LDI + (lane >> 5) * 8;
+#pragma unroll
+        for (int c16 = 0; c16 < CIN / 16; ++c16) {
+          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(rowp + c16 * 16);
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) {
+            const bf16x8_t bw = *reinterpret_cast<const bf16x8_t*>(
+                sW + (tn * 32 + (lane & 31)) * LDW + tap * CIN + c16 * 16 + (lane >> 5) * 8);
+            acc[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[tn], 0, 0, 0);
+          }
+        }
+      }
+      // epilogue: lane holds output channel co for 16 pixels of the group
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const int co = tn * 32 + (lane & 31);
+        const float bias = (MODE != 2 && args.bias) ? args.bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int x = 32 * g + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int64_t pix = ((int64_t)b * H + y) * W + x;
+          const float v = acc[tn][r] + bias;
+          if constexpr (MODE == 0) {
+            if (args.u_out) args.u_out[pix * COUT + co] = v;
+            args.a_out[pix * COUT + co] = to_bf16(gelu(v));
+          } else if constexpr (MODE == 1) {
+            if (co < args.c0) {
+              const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
+              const float yv = args.x_res[o] + v;
+              args.y_out[o] = yv;
+              if (args.target) {
+                const float diff = yv - args.target[o];
+                loss_local += diff * diff;
+                args.a_out[pix * COUT + co] = to_bf16(args.grad_scale * diff);
+              }
+            } else if (args.target) {
+              args.a_out[pix * COUT + co] = 0;
+            }
+          } else {
+            const float gp = gelu_grad(args.u_prev[pix * COUT + co]);
+            args.a_out[pix * COUT + co] = to_bf16(v * gp);
+          }
+        }
+      }
+    }
+    __syncthreads();                      // all reads of row y-1's slot are done
+    if (y + 1 < y1) {
+      load_row(y + 2);
+      __syncthreads();
+    }
+  }
+  if constexpr (MODE == 1) {
+    if (args.loss_part) {
+      for (int o = 32; o > 0; o >>= 1) loss_local += __shfl_xor(loss_local, o);
+      if (lane == 0) red[wave] = loss_local;
+      __syncthreads();
+      if (tid == 0)
+        args.loss_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] =
+            red[0] + red[1] + red[2] + red[3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// weight gradient: part[chunk][tap][co][ci] = sum_{p in chunk} du[p][co] * in[p + tap][ci]
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
+  constexpr int KS = 32;                  // pixels per k-step (one row segment)
+  constexpr int LDA = COUT + 4, LDB = CIN + 4;
+  __shared__ float sA[KS * LDA];
+  __shared__ float sB[KS * LDB];
+  constexpr int WM = COUT / 32, WN = CIN / 32;
+  const int H = args.H, W = args.W;
+  const int chunk = blockIdx.x, tap = blockIdx.y;
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t npix = (int64_t)args.batch * H * W;
+  const int64_t p0 = (int64_t)chunk * args.chunk_pixels;
+  const int64_t p1 = min(p0 + (int64_t)args.chunk_pixels, npix);
+  const bool active = wave < WM * WN;
+  const int wm = wave / WN, wn = wave % WN;
+
+  f32x16_t acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+  for (int64_t pb = p0; pb < p1; pb += KS) {
+    __syncthreads();
+    for (int v = tid; v < KS * COUT / 8; v += 256) {
+      const int k = v / (COUT / 8), c8 = v % (COUT / 8);
+      const int64_t p = pb + k;
+      u32x4 w = {0, 0, 0, 0};
+      if (p < p1) w = *reinterpret_cast<const u32x4*>(args.du + p * COUT + c8 * 8);
+      float* d = sA + k * LDA + c8 * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[2 * q] = from_bf16((uint16_t)(w[q] & 0xFFFF));
+        d[2 * q + 1] = from_bf16((uint16_t)(w[q] >> 16));
+      }
+    }
+    for (int v = tid; v < KS * CIN / 8; v += 256) {
+      const int k = v / (CIN / 8), c8 = v % (CIN / 8);
+      const int64_t p = pb + k;
+      u32x4 w = {0, 0, 0, 0};
+      if (p < p1) {
+        const int64_t bimg = p / ((int64_t)H * W);
+        const int yy = (int)((p / W) % H), xx = (int)(p % W);
+        const int64_t q = (bimg * H + wrap(yy + dy, H)) * W + wrap(xx + dx, W);
+        w = *reinterpret_cast<const u32x4*>(args.in + q * CIN + c8 * 8);
+      }
+      float* d = sB + k * LDB + c8 * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[2 * q] = from_bf16((uint16_t)(w[q] & 0xFFFF));
+        d[2 * q + 1] = from_bf16((uint16_t)(w[q] >> 16));
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < KS; kk += 2) {
+        const float a = sA[(kk + (lane >> 5)) * LDA + wm * 32 + (lane & 31)];
+        const float bb = sB[(kk + (lane >> 5)) * LDB + wn * 32 + (lane & 31)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+      }
+    }
+  }
+  if (active) {
+    float* out = args.part + ((int64_t)chunk * 9 + tap) * COUT * CIN;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int co = wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+      const int ci = wn * 32 + (lane & 31);
+      out[co * CIN + ci] = acc[r];
+    }
+  }
+}
+
+// bias gradient partials: part[chunk][co] = sum_{p in chunk} du[p][co]
+__global__ __launch_bounds__(256) void k_bias_grad_part(const uint16_t* __restrict__ du,
+                                                       int64_t npix, int cout, int chunk_pixels,
+                                                       float* __restrict__ part) {
+  __shared__ float s[256];
+  const int groups = 256 / cout;
+  const int co = threadIdx.x % cout, grp = threadIdx.x / cout;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk_pixels;
+  const int64_t p1 = min(p0 + (int64_t)chunk_pixels, npix);
+  float acc = 0.0f;
+  if (grp < groups)
+    for (int64_t p = p0 + grp; p < p1; p += groups) acc += from_bf16(du[p * cout + co]);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    float t = 0.0f;
+    for (int gg = 0; gg < groups; ++gg) t += s[gg * cout + threadIdx.x];
+    part[(int64_t)blockIdx.x * cout + threadIdx.x] = t;
+  }
+}
+
+// grad[i] = sum over chunks of part[chunk][i] (fixed order), FP64 accumulation
+__global__ void k_reduce_chunks(const float* __restrict__ part, int64_t n, int chunks,
+                                float* __restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + i];
+  grad[i] = (float)s;
+}
+
+// wgrad partial layout [tap][co][ci] -> parameter layout [co][tap][ci]
+__global__ void k_reduce_wgrad(const float* __restrict__ part, int cout, int cin, int chunks,
+                               float* __restrict__ grad) {
+  const int64_t n = 9LL * cout * cin;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int tap = (int)(i / ((int64_t)cout * cin));
+  const int co = (int)((i / cin) % cout), ci = (int)(i % cin);
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + i];
+  grad[((int64_t)co * 9 + tap) * cin + ci] = (float)s;
+}
+
+__global__ void k_sum_loss(const float* __restrict__ part, int n, double scale,
+                           double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+  }
+}
+
+// Adam (Kingma & Ba, 2015) on the flat FP32 master parameters.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float corr1, float corr2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / corr1, vh = vi / corr2;
+  p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// bf16 copies of one layer's weights: wk[co][tap*CIN + ci] and the flipped transpose used
+// by the input gradient, wf[ci][(8 - tap)*COUT + co].
+__global__ void k_make_bf16_weights(const float* __restrict__ w, int cout, int cin,
+                                    uint16_t* __restrict__ wk, uint16_t* __restrict__ wf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 9LL * cout * cin) return;
+  const int co = (int)(i / (9LL * cin)), tap = (int)((i / cin) % 9), ci = (int)(i % cin);
+  const uint16_t h = to_bf16(w[i]);
+  wk[i] = h;
+  wf[((int64_t)ci * 9 + (8 - tap)) * cout + co] = h;
+}
+
+// ---------------------------------------------------------------------------------------
+// host launchers
+
+size_t conv_smem_bytes(int cin, int cout, int W) {
+  return (size_t)cout * (9 * cin + 8) * 2 + (size_t)3 * (W + 2) * (cin + 8) * 2;
+}
+
+template <int CIN, int COUT, int MODE>
+static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t s) {
+  const size_t shm = conv_smem_bytes(CIN, COUT, a.W);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_conv<CIN, COUT, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid((a.H + a.rows - 1) / a.rows, a.batch);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), grid, dim3(256), shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv(int cin, int cout, int mode, const ConvArgs& a, hipStream_t s) {
+#define SG_CONV(CI, CO, MD) \
+  if (cin == CI && cout == CO && mode == MD) return launch_conv_t<CI, CO, MD>(a, s);
+  SG_CONV(32, 32, 0) SG_CONV(32, 64, 0) SG_CONV(64, 32, 0) SG_CONV(64, 64, 0)
+  SG_CONV(32, 32, 1) SG_CONV(64, 32, 1)
+  SG_CONV(32, 32, 2) SG_CONV(32, 64, 2) SG_CONV(64, 32, 2) SG_CONV(64, 64, 2)
+#undef SG_CONV
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t s) {
+  dim3 grid(chunks, 9);
+#define SG_WG(CI, CO)                                                                \
+  if (cin == CI && cout == CO) {                                                     \
+    hipLaunchKernelGGL((k_conv_wgrad<CI, CO>), grid, dim3(256), 0, s, a);            \
+    return hipGetLastError();                                                        \
+  }
+  SG_WG(32, 32) SG_WG(32, 64) SG_WG(64, 32) SG_WG(64, 64)
+#undef SG_WG
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_input(const float* x, uint16_t* a, int batch, int c0, int H, int W, int cp,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)batch * H * W;
+  hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, a,
+                     batch, c0, H, W, cp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const uint16_t* du, int64_t npix, int cout, int chunk_pixels,
+                            int chunks, float* part, float* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_bias_grad_part, dim3(chunks), dim3(256), 0, s, du, npix, cout,
+                     chunk_pixels, part);
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((cout + 255) / 256), dim3(256), 0, s, part,
+                     (int64_t)cout, chunks, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_wgrad(const float* part, int cout, int cin, int chunks, float* grad,
+                               hipStream_t s) {
+  const int64_t n = 9LL * cout * cin;
+  hipLaunchKernelGGL(k_reduce_wgrad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     cout, cin, chunks, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_loss(const float* part, int n, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, s, part, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, float corr1, float corr2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n,
+                     lr, b1, b2, eps, corr1, corr2);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_bf16_weights(const float* w, int cout, int cin, uint16_t* wk,
+                                    uint16_t* wf, hipStream_t s) {
+  const int64_t n = 9LL * cout * cin;
+  hipLaunchKernelGGL(k_make_bf16_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w,
+                     cout, cin, wk, wf);
+  return hipGetLastError();
+}
+
+}  // namespace sg
+}  // namespace ensf

@@ -10,16 +10,21 @@ from paper_2407_12168_amd import ensf
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ensf.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_entry_points():
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ensf_status|void|const char\*)\s+(ensf_\w+)\s*\(",
-                                 txt, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        names |= set(re.findall(r"^\s*(?:ensf_status|void|const char\*|int64_t)\s+(ensf_\w+)\s*\(",
+                                open(h).read(), flags=re.M))
+    return sorted(names)
 
 
-def test_header_declares_the_binding_names():
-    assert declared_entry_points() == sorted(ensf.EXPORTS)
+def test_headers_declare_the_binding_names():
+    from paper_2407_12168_amd import surrogate
+    assert declared_entry_points() == sorted(ensf.EXPORTS + surrogate.EXPORTS)
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,107 @@
+"""GPU conv surrogate (BF16 MFMA forward / input gradient, FP32 MFMA weight gradient,
+Adam) against the FP64 oracle of oracle/conv.py on the same parameters.
+
+Tolerances: BF16 weights and activations give ~2^-9 relative rounding per layer, so
+  forward output y = x + net(x):   rel-L2(net) <= 2e-2
+  every parameter gradient:        rel-L2 per tensor <= 5e-2
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import conv as C
+from paper_2407_12168_amd import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _setup(dev, h, w, batch, seed=0, width=64, layers=6):
+    rng = np.random.default_rng(seed)
+    params = C.init_params(rng, c0=2, width=width, layers=layers)
+    params = [(wt, 0.05 * rng.standard_normal(b.shape)) for wt, b in params]
+    x = rng.standard_normal((batch, 2, h, w)).astype(np.float32)
+    tgt = (x + 0.3 * rng.standard_normal(x.shape)).astype(np.float32)
+    sur = S.Surrogate(c0=2, width=width, layers=layers, h=h, w=w, max_batch=max(batch, 2))
+    S.ensf_surrogate_set_params(sur.handle, C.flatten(params))
+    return sur, params, x, tgt
+
+
+def test_param_roundtrip_and_count(dev):
+    sur, params, _, _ = _setup(dev, 8, 32, 1)
+    got = S.ensf_surrogate_get_params(sur.handle)
+    assert got.size == C.n_params(params) == S.ensf_surrogate_num_params(sur.handle)
+    np.testing.assert_array_equal(got, C.flatten(params).astype(np.float32))
+    sur.destroy()
+
+
+@pytest.mark.parametrize("h,w,batch", [(16, 32, 3), (128, 128, 2)])
+def test_forward_matches_oracle(dev, h, w, batch):
+    sur, params, x, _ = _setup(dev, h, w, batch, seed=1)
+    xg = torch.from_numpy(x).to(dev)
+    y = torch.empty_like(xg)
+    S.ensf_surrogate_forward(sur.handle, xg, y)
+    torch.cuda.synchronize()
+    want = C.forward(params, x.astype(np.float64))
+    got = y.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm((got - x) - (want - x)) / np.linalg.norm(want - x)
+    print(f"forward {h}x{w} batch {batch}: net rel-L2 {err:.2e}")
+    assert err <= 2e-2
+    sur.destroy()
+
+
+def test_forward_in_chunks_larger_than_workspace(dev):
+    sur, params, x, _ = _setup(dev, 16, 32, 2, seed=2)
+    rng = np.random.default_rng(3)
+    xs = rng.standard_normal((7, 2, 16, 32)).astype(np.float32)
+    xg = torch.from_numpy(xs).to(dev)
+    y = torch.empty_like(xg)
+    S.ensf_surrogate_forward(sur.handle, xg, y)       # max_batch 2 -> 4 chunks
+    y1 = torch.empty_like(xg[:1])
+    S.ensf_surrogate_forward(sur.handle, xg[6:7].contiguous(), y1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y[6:7].cpu().numpy(), y1.cpu().numpy())
+    sur.destroy()
+
+
+def test_gradients_match_oracle(dev):
+    sur, params, x, tgt = _setup(dev, 16, 32, 3, seed=4)
+    grad = torch.empty(C.n_params(params), device=dev)
+    loss = S.ensf_surrogate_grad(sur.handle, torch.from_numpy(x).to(dev),
+                                 torch.from_numpy(tgt).to(dev), grad)
+    want_loss, want = C.loss_and_grads(params, x.astype(np.float64), tgt.astype(np.float64))
+    assert abs(loss - want_loss) <= 2e-2 * want_loss
+    g = C.unflatten(grad.cpu().numpy())
+    for l, ((gw, gb), (ww, wb)) in enumerate(zip(g, want)):
+        ew = np.linalg.norm(gw - ww) / np.linalg.norm(ww)
+        eb = np.linalg.norm(gb - wb) / max(np.linalg.norm(wb), 1e-30)
+        print(f"layer {l}: weight-grad rel-L2 {ew:.2e}, bias-grad rel-L2 {eb:.2e}")
+        assert ew <= 5e-2 and eb <= 5e-2
+    sur.destroy()
+
+
+def test_adam_training_follows_oracle_and_reduces_loss(dev):
+    sur, params, x, tgt = _setup(dev, 16, 32, 4, seed=5)
+    xg, tg = torch.from_numpy(x).to(dev), torch.from_numpy(tgt).to(dev)
+    state = [[(np.zeros_like(p), np.zeros_like(p)) for p in layer] for layer in params]
+    p_or = params
+    losses_gpu, losses_or = [], []
+    for step in range(1, 6):
+        losses_gpu.append(S.ensf_surrogate_train_step(sur.handle, xg, tg, 1e-3))
+        lo, gr = C.loss_and_grads(p_or, x.astype(np.float64), tgt.astype(np.float64))
+        losses_or.append(lo)
+        p_or = C.adam_step(p_or, gr, state, 1e-3, step)
+    print("loss gpu", np.round(losses_gpu, 5), "oracle", np.round(losses_or, 5))
+    np.testing.assert_allclose(losses_gpu, losses_or, rtol=2e-2)
+    assert losses_gpu[-1] < losses_gpu[0]
+    got = C.unflatten(S.ensf_surrogate_get_params(sur.handle))
+    for (gw, gb), (ww, wb) in zip(got, p_or):
+        assert np.linalg.norm(gw - ww) <= 2e-2 * np.linalg.norm(ww)
+    sur.destroy()
