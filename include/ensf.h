@@ -161,6 +161,10 @@ ensf_status ensf_destroy(ensf_ctx* ctx);
 
 const char* ensf_status_string(ensf_status s);
 
+/* Text of the HIP error behind the calling thread's most recent ENSF_EHIP / ENSF_ENOMEM
+   (from any entry point of this library), or "" if none. */
+const char* ensf_last_error_string(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,17 @@ hipError_t set_softmax_smem_limit(size_t bytes);
 
 using namespace ensf;
 
+namespace ensf {
+namespace {
+thread_local hipError_t g_last_error = hipSuccess;
+}
+void record_hip_error(hipError_t e) {
+  g_last_error = e;
+  (void)hipGetLastError();
+}
+void clear_stale_hip_error() { (void)hipGetLastError(); }
+}  // namespace ensf
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -90,7 +101,10 @@ struct ensf_ctx {
 
 namespace {
 
-ensf_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? ENSF_ENOMEM : ENSF_EHIP; }
+ensf_status hip_fail(hipError_t e) {
+  ensf::record_hip_error(e);
+  return e == hipErrorOutOfMemory ? ENSF_ENOMEM : ENSF_EHIP;
+}
 
 #define HIP_TRY(expr)                               \
   do {                                              \
@@ -468,6 +482,7 @@ ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, h
     ensf_status st = validate(p);
     if (st != ENSF_OK) return st;
   }
+  clear_stale_hip_error();
   HIP_TRY(hipSetDevice(c->device));
   Plan plan;
   ensf_status st = build_plan(c, probs, plan, force);
@@ -607,6 +622,7 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   ensf_status st = validate(p);
   if (st != ENSF_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  clear_stale_hip_error();
   HIP_TRY(hipSetDevice(ctx->device));
   std::vector<ensf_problem> probs{p};
   Plan plan;
@@ -640,6 +656,7 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
 ensf_status ensf_rng_normal(uint64_t seed, uint32_t filter_id, uint32_t step, uint32_t particle,
                             int64_t n, float* d_out, uint32_t* d_raw_words, void* stream) {
   if (!d_out || n < 1 || n > (int64_t(1) << 34)) return ENSF_EINVAL;
+  clear_stale_hip_error();
   HIP_TRY(launch_rng_normal(seed, filter_id, step, particle, n, d_out, d_raw_words,
                             reinterpret_cast<hipStream_t>(stream)));
   return ENSF_OK;
@@ -648,6 +665,7 @@ ensf_status ensf_rng_normal(uint64_t seed, uint32_t filter_id, uint32_t step, ui
 ensf_status ensf_ensemble_stats(const float* d_ens, int32_t n, int64_t dim, float* d_mean,
                                 float* d_spread, void* stream) {
   if (!d_ens || !d_mean || !d_spread || n < 2 || dim < 1) return ENSF_EINVAL;
+  clear_stale_hip_error();
   HIP_TRY(launch_stats(d_ens, n, dim, d_mean, d_spread, reinterpret_cast<hipStream_t>(stream)));
   return ENSF_OK;
 }
@@ -751,6 +769,10 @@ ensf_status ensf_destroy(ensf_ctx* ctx) {
   if (ctx->tab_event) (void)hipEventDestroy(ctx->tab_event);
   delete ctx;
   return ENSF_OK;
+}
+
+const char* ensf_last_error_string(void) {
+  return g_last_error == hipSuccess ? "" : hipGetErrorString(g_last_error);
 }
 
 const char* ensf_status_string(ensf_status s) {

@@ -76,6 +76,11 @@ inline int wx_bp(int c) {
 }
 constexpr int kBK = 32;
 
+// Remembers the HIP error behind the calling thread's latest failed call
+// (ensf_last_error_string) and clears HIP's sticky last-error state.
+void record_hip_error(hipError_t e);
+void clear_stale_hip_error();
+
 // Host-callable launchers (ensf_kernels.hip).
 hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipStream_t s);
 hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ldn, hipStream_t s);

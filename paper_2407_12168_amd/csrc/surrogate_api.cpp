@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/ensf_surrogate.h"
+#include "ensf_internal.h"
 #include "surrogate_internal.h"
 
 using namespace ensf::sg;
@@ -20,7 +21,10 @@ constexpr int kChunkPixels = 4096;  // pixels per weight-gradient partial
 
 inline int pad_ch(int c) { return c <= 32 ? 32 : 64; }
 
-ensf_status hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? ENSF_ENOMEM : ENSF_EHIP; }
+ensf_status hip_fail(hipError_t e) {
+  ensf::record_hip_error(e);
+  return e == hipErrorOutOfMemory ? ENSF_ENOMEM : ENSF_EHIP;
+}
 
 #define HIP_TRY(expr)                          \
   do {                                         \
@@ -184,7 +188,8 @@ ensf_status ensf_surrogate_create(int32_t c0, int32_t width, int32_t layers, int
   if (c0 < 1 || c0 > 32 || (width != 32 && width != 64) || layers < 2 || h < 1 || w < 32 ||
       w % 32 != 0 || max_batch < 1)
     return ENSF_EINVAL;
-  if (conv_smem_bytes(64, 64, w) > 160 * 1024) return ENSF_EUNSUPPORTED;
+  if (conv_smem_bytes(64, 64, w) + 1024 > 160 * 1024) return ENSF_EUNSUPPORTED;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(device));
   ensf_surrogate* s = new ensf_surrogate();
   s->c0 = c0;
@@ -264,6 +269,7 @@ int64_t ensf_surrogate_num_params(const ensf_surrogate* s) {
 
 ensf_status ensf_surrogate_set_params(ensf_surrogate* s, const float* h_params) {
   if (!s || !h_params) return ENSF_EINVAL;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(s->device));
   std::vector<float> flat;
   to_gpu_layout(s, h_params, flat);
@@ -279,6 +285,7 @@ ensf_status ensf_surrogate_set_params(ensf_surrogate* s, const float* h_params) 
 
 ensf_status ensf_surrogate_get_params(ensf_surrogate* s, float* h_params) {
   if (!s || !h_params) return ENSF_EINVAL;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(s->device));
   HIP_TRY(hipDeviceSynchronize());
   std::vector<float> flat(s->nflat);
@@ -290,6 +297,7 @@ ensf_status ensf_surrogate_get_params(ensf_surrogate* s, float* h_params) {
 ensf_status ensf_surrogate_forward(ensf_surrogate* s, const float* d_x, float* d_y,
                                    int32_t batch, void* stream) {
   if (!s || !d_x || !d_y || batch < 1) return ENSF_EINVAL;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(s->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t per = (int64_t)s->c0 * s->H * s->W;
@@ -304,6 +312,7 @@ ensf_status ensf_surrogate_forward(ensf_surrogate* s, const float* d_x, float* d
 ensf_status ensf_surrogate_grad(ensf_surrogate* s, const float* d_x, const float* d_target,
                                 int32_t batch, float* d_grad, double* h_loss, void* stream) {
   if (!s || !d_x || !d_target || !d_grad || batch < 1 || batch > s->max_batch) return ENSF_EINVAL;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(s->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   ensf_status rc = gradient(s, d_x, d_target, batch, st);
@@ -322,6 +331,7 @@ ensf_status ensf_surrogate_train_step(ensf_surrogate* s, const float* d_x,
                                       double* h_loss, void* stream) {
   if (!s || !d_x || !d_target || batch < 1 || batch > s->max_batch || !(lr > 0.0f))
     return ENSF_EINVAL;
+  ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(s->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   ensf_status rc = gradient(s, d_x, d_target, batch, st);

@@ -340,12 +340,12 @@ size_t conv_smem_bytes(int cin, int cout, int W) {
 template <int CIN, int COUT, int MODE>
 static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t s) {
   const size_t shm = conv_smem_bytes(CIN, COUT, a.W);
-  static bool attr_set = false;
-  if (!attr_set) {
+  static size_t attr_bytes = 0;
+  if (shm > 64 * 1024 && shm > attr_bytes) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_conv<CIN, COUT, MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_bytes = shm;
   }
   dim3 grid((a.H + a.rows - 1) / a.rows, a.batch);
   hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), grid, dim3(256), shm, s, a);

@@ -23,6 +23,8 @@ class EnsfError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
         msg = _lib().ensf_status_string(status).decode() if _LIB is not None else str(status)
+        if _LIB is not None and status in (ENSF_EHIP, ENSF_ENOMEM):
+            msg += f" [{_LIB.ensf_last_error_string().decode()}]"
         super().__init__(f"{what}: {msg} (status {status})" if what else msg)
 
 
@@ -46,7 +48,7 @@ _LIB = None
 EXPORTS = ("ensf_default_options", "ensf_create", "ensf_analysis", "ensf_analysis_batched",
            "ensf_score", "ensf_rng_normal", "ensf_ensemble_stats", "ensf_sync_status",
            "ensf_autotune", "ensf_profile_phases", "ensf_phase_times", "ensf_destroy",
-           "ensf_status_string")
+           "ensf_status_string", "ensf_last_error_string")
 
 
 def _lib():
@@ -75,8 +77,11 @@ def _lib():
         L.ensf_destroy.argtypes = [vp]
         L.ensf_status_string.argtypes = [ctypes.c_int]
         L.ensf_status_string.restype = ctypes.c_char_p
+        L.ensf_last_error_string.argtypes = []
+        L.ensf_last_error_string.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("ensf_default_options", "ensf_status_string"):
+            if name not in ("ensf_default_options", "ensf_status_string",
+                            "ensf_last_error_string"):
                 getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
