@@ -23,8 +23,8 @@ def declared_entry_points():
 
 
 def test_headers_declare_the_binding_names():
-    from paper_2407_12168_amd import surrogate
-    assert declared_entry_points() == sorted(ensf.EXPORTS + surrogate.EXPORTS)
+    from paper_2407_12168_amd import sqg, surrogate
+    assert declared_entry_points() == sorted(ensf.EXPORTS + surrogate.EXPORTS + sqg.EXPORTS)
 
 
 @pytest.fixture(scope="module")
