@@ -1,0 +1,169 @@
+"""Data-assimilation cycle of the paper's framework (Fig. 1, Sec. III; twin experiment of
+Sec. IV-A): forecast every member, observe the truth, run the EnSF analysis, repeat.
+
+Everything runs on the GPU through libensf: the truth and the physics forecast are the
+FP64 SQG model (ensf_sqg), the learned forecast is the conv surrogate (ensf_surrogate),
+the analysis is ensf_analysis.  Host code only draws the synthetic observation noise and
+the initial ensemble and orchestrates the calls.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class CycleConfig:
+    grid: int = 128
+    members: int = 512
+    cycles: int = 50
+    obs_stride: int = 4          # observe every 4th grid point in x and y on both levels
+    sigma_o: float = 0.05
+    obs_op: str = "linear"       # the paper's twin experiment observes the state itself
+    pseudo_steps: int = 400      # EM-stable for sigma_o = 0.05
+    precision: str = "bf16x3"
+    spread_relax: float = 1.0    # relax the analysis spread to the prior spread
+    sqg_dt: float = 0.025
+    steps_per_cycle: int = 20    # forecast length between analyses (0.5 time units)
+    spinup_steps: int = 400
+    init_spread: float = 0.5     # initial ensemble perturbation std relative to the truth
+    seed: int = 2412
+    filter_seed: int = 12173
+
+
+@dataclass
+class CycleResult:
+    rmse: list = field(default_factory=list)          # analysis mean vs truth, per cycle
+    rmse_forecast: list = field(default_factory=list)  # forecast mean vs truth, per cycle
+    spread: list = field(default_factory=list)
+    forecast_s: list = field(default_factory=list)
+    analysis_s: list = field(default_factory=list)
+
+
+def obs_indices(grid, stride):
+    lv, iy, ix = np.meshgrid(np.arange(2), np.arange(0, grid, stride), np.arange(0, grid, stride),
+                             indexing="ij")
+    return np.sort((lv * grid * grid + iy * grid + ix).reshape(-1)).astype(np.int32)
+
+
+def spun_up_states(sqg, count, cfg, rng, dev):
+    """`count` SQG states: red-spectrum random fields integrated for spinup_steps."""
+    import torch
+
+    import workloads
+    x = workloads.smooth_fields(rng, 2 * count, cfg.grid, cfg.grid).reshape(count, 2, cfg.grid,
+                                                                          cfg.grid)
+    xg = torch.from_numpy(x).to(dev)
+    sqg.run(xg, xg, cfg.spinup_steps)
+    return xg
+
+
+def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
+    """forecast: "sqg" (the physics model, which is also the truth's model), "conv" (the
+    trained surrogate) or "persistence" (no forecast model: the analysis is carried over)."""
+    import torch
+
+    import workloads
+    from . import ensf
+    from .sqg import SQGModel
+    from .surrogate import ensf_surrogate_forward
+
+    dev = dev or torch.device("cuda:0")
+    rng = np.random.default_rng(cfg.seed)
+    n, d = cfg.grid, 2 * cfg.grid * cfg.grid
+    res = CycleResult()
+    with SQGModel(n=n, dt=cfg.sqg_dt, max_batch=min(cfg.members, 256)) as sqg:
+        truth = spun_up_states(sqg, 1, cfg, rng, dev)              # (1, 2, n, n) float64
+        pert = workloads.smooth_fields(rng, 2 * cfg.members, n, n).reshape(cfg.members, -1)
+        ens = (truth.reshape(1, -1).cpu().numpy() + cfg.init_spread * pert).astype(np.float32)
+        ens = torch.from_numpy(ens).to(dev)                         # (N, d) float32
+        post = torch.empty_like(ens)
+        idx = torch.from_numpy(obs_indices(n, cfg.obs_stride)).to(dev)
+        ctx = ensf.Context(precision=cfg.precision, obs_op=cfg.obs_op,
+                           spread_relax=cfg.spread_relax)
+        try:
+            for c in range(cfg.cycles):
+                sqg.run(truth, truth, cfg.steps_per_cycle)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                states = ens.view(cfg.members, 2, n, n)
+                if forecast == "sqg":
+                    sqg.run(states, states, cfg.steps_per_cycle)
+                elif forecast == "conv":
+                    ensf_surrogate_forward(surrogate.handle, states, states)
+                elif forecast != "persistence":
+                    raise ValueError(forecast)
+                torch.cuda.synchronize()
+                res.forecast_s.append(time.perf_counter() - t0)
+                tv = truth.reshape(-1).float()
+                clean = torch.atan(tv[idx.long()]) if cfg.obs_op == "arctan" else tv[idx.long()]
+                noise = torch.from_numpy(rng.standard_normal(idx.numel()).astype(np.float32)).to(dev)
+                y = (clean + cfg.sigma_o * noise).contiguous()
+                res.rmse_forecast.append(float(torch.sqrt(torch.mean((ens.mean(0) - tv) ** 2))))
+                t0 = time.perf_counter()
+                ensf.ensf_analysis(ctx.handle, ens, post, idx, y, cfg.sigma_o, cfg.pseudo_steps,
+                                   cfg.filter_seed, c)
+                st, nbad = ensf.ensf_sync_status(ctx.handle)
+                res.analysis_s.append(time.perf_counter() - t0)
+                if st != ensf.ENSF_OK:
+                    raise RuntimeError(f"analysis status {st} at cycle {c} ({nbad} non-finite)")
+                ens, post = post, ens
+                res.rmse.append(float(torch.sqrt(torch.mean((ens.mean(0) - tv) ** 2))))
+                res.spread.append(float(torch.sqrt(torch.mean(ens.var(0)))))
+                if log:
+                    log(f"cycle {c}: forecast rmse {res.rmse_forecast[-1]:.4f}, analysis rmse "
+                        f"{res.rmse[-1]:.4f}, spread {res.spread[-1]:.4f}, forecast "
+                        f"{res.forecast_s[-1] * 1e3:.1f} ms, analysis {res.analysis_s[-1] * 1e3:.1f} ms")
+        finally:
+            ctx.destroy()
+    return res
+
+
+def training_pairs(count, cfg, dev, seed=None):
+    """(x, SQG(x)) pairs over one forecast interval from seeded spun-up random fields."""
+    import torch
+
+    from .sqg import SQGModel
+    rng = np.random.default_rng(cfg.seed + 1 if seed is None else seed)
+    with SQGModel(n=cfg.grid, dt=cfg.sqg_dt, max_batch=min(count, 256)) as sqg:
+        x = spun_up_states(sqg, count, cfg, rng, dev)
+        y = torch.empty_like(x)
+        sqg.run(x, y, cfg.steps_per_cycle)
+        torch.cuda.synchronize()
+    return x.float().contiguous(), y.float().contiguous()
+
+
+def train_surrogate(x, y, epochs=30, batch=32, lr=1e-3, seed=0, log=None, val=None):
+    """Trains the conv surrogate on pairs (x, y) with the library's Adam; returns it and
+    the per-epoch mean training loss (and validation loss if val = (xv, yv))."""
+    import torch
+
+    from .surrogate import Surrogate, ensf_surrogate_forward, ensf_surrogate_train_step
+    n = x.shape[0]
+    sur = Surrogate(c0=x.shape[1], width=64, layers=6, h=x.shape[2], w=x.shape[3],
+                    max_batch=batch, seed=seed)
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(x.device)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            sel = perm[b0:b0 + batch]
+            loss = ensf_surrogate_train_step(sur.handle, x[sel].contiguous(), y[sel].contiguous(),
+                                             lr, want_loss=(b0 == 0))
+            if loss is not None:
+                tot += loss
+                cnt += 1
+        entry = {"epoch": ep, "train_loss_first_batch": tot / max(cnt, 1)}
+        if val is not None:
+            xv, yv = val
+            vl = []
+            for b0 in range(0, xv.shape[0], batch):
+                pred = torch.empty_like(xv[b0:b0 + batch])
+                ensf_surrogate_forward(sur.handle, xv[b0:b0 + batch].contiguous(), pred)
+                vl.append(float(torch.mean((pred - yv[b0:b0 + batch]) ** 2)))
+            entry["val_mse"] = float(np.mean(vl))
+        hist.append(entry)
+        if log:
+            log(str(entry))
+    return sur, hist
