@@ -43,6 +43,7 @@ struct TileChoice {
   int gram = kGram128;
   int wx = kWx128;
   double split_scale = 1.0;  // multiplies the default split-K count
+  int bk = 32;               // k-step depth of the MFMA main loops (32 or 64)
 };
 
 struct GraphKey {
@@ -186,11 +187,11 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   // split-K: this problem's share of ~1024 workgroups (enough to fill the device), chunks
   // of at least 4 k-steps, and partial sums no larger than a quarter of the operand bytes
   int64_t s = std::max<int64_t>(1, (int64_t)std::ceil(wg_target / (double)tiles));
-  s = std::min<int64_t>(s, P.ldz / (4 * kBK));
+  s = std::min<int64_t>(s, P.ldz / (4 * kMaxBK));
   s = std::min<int64_t>(s, std::max<int64_t>(1, (P.Mp + P.N) * P.ldz / (4 * (int64_t)P.Mp * P.N)));
   s = std::max<int64_t>(1, (int64_t)std::llround(s * tc.split_scale));
-  s = std::min<int64_t>(s, P.ldz / kBK);
-  P.kchunk = round_up(ceil_div(P.ldz, s), kBK);
+  s = std::min<int64_t>(s, P.ldz / kMaxBK);
+  P.kchunk = round_up(ceil_div(P.ldz, s), kMaxBK);
   P.S = (int32_t)ceil_div(P.ldz, P.kchunk);
   P.wx_tp = (int32_t)ceil_div(P.Mp, wx_bp(tc.wx));
   P.wx_te = (int32_t)ceil_div(P.d, wx_be(tc.wx));
@@ -378,9 +379,9 @@ ensf_status ensure_softmax_smem(ensf_ctx* c, int max_ldn) {
 ensf_status enqueue_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStream_t s) {
   const int prec = c->opt.precision;
   for (int k = 0; k < plan.kmax; ++k) {
-    HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, k, s));
+    HIP_TRY(launch_gram(prec, plan.tiles.gram, plan.tiles.bk, u.gram, k, s));
     HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
-    HIP_TRY(launch_wx(prec, plan.tiles.wx, false, u.wx, k, c->d_counters, s));
+    HIP_TRY(launch_wx(prec, plan.tiles.wx, plan.tiles.bk, false, u.wx, k, c->d_counters, s));
   }
   return ENSF_OK;
 }
@@ -416,11 +417,11 @@ ensf_status enqueue_steps_profiled(ensf_ctx* c, const Plan& plan, const Uploaded
   for (int k = 0; k < plan.kmax; ++k) {
     hipEvent_t* ev = &c->events[first + 4 * k];
     HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, k, s));
+    HIP_TRY(launch_gram(prec, plan.tiles.gram, plan.tiles.bk, u.gram, k, s));
     HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
     HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_wx(prec, plan.tiles.wx, false, u.wx, k, c->d_counters, s));
+    HIP_TRY(launch_wx(prec, plan.tiles.wx, plan.tiles.bk, false, u.wx, k, c->d_counters, s));
     HIP_TRY(hipEventRecord(ev[3], s));
   }
   c->events_used = need;
@@ -527,8 +528,10 @@ void load_tune_cache(ensf_ctx* c) {
     if (end == std::string::npos) break;
     const std::string key = txt.substr(pos + 1, end - pos - 1);
     TileChoice tc;
-    if (sscanf(txt.c_str() + end + 1, " : [ %d , %d , %lf ]", &tc.gram, &tc.wx, &tc.split_scale) == 3 &&
-        tc.gram >= 0 && tc.gram < kNumGram && tc.wx >= 0 && tc.wx < kNumWx)
+    const int got = sscanf(txt.c_str() + end + 1, " : [ %d , %d , %lf , %d ]", &tc.gram, &tc.wx,
+                           &tc.split_scale, &tc.bk);
+    if (got >= 3 && tc.gram >= 0 && tc.gram < kNumGram && tc.wx >= 0 && tc.wx < kNumWx &&
+        (tc.bk == 32 || tc.bk == 64))
       c->tune[key] = tc;
     pos = end + 1;
   }
@@ -541,8 +544,8 @@ void save_tune_cache(ensf_ctx* c) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (const auto& kv : c->tune)
-    fprintf(fp, "  \"%s\": [%d, %d, %.3f]%s\n", kv.first.c_str(), kv.second.gram, kv.second.wx,
-            kv.second.split_scale, ++i < c->tune.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %.3f, %d]%s\n", kv.first.c_str(), kv.second.gram,
+            kv.second.wx, kv.second.split_scale, kv.second.bk, ++i < c->tune.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
 }
@@ -645,9 +648,9 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   st = prep_problem(ctx, P, true, s);
   if (st != ENSF_OK) return st;
   const int prec = ctx->opt.precision;
-  HIP_TRY(launch_gram(prec, plan.tiles.gram, u.gram, -1, s));
+  HIP_TRY(launch_gram(prec, plan.tiles.gram, 32, u.gram, -1, s));
   HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
-  HIP_TRY(launch_wx(prec, plan.tiles.wx, true, u.wx, -1, ctx->d_counters, s));
+  HIP_TRY(launch_wx(prec, plan.tiles.wx, 32, true, u.wx, -1, ctx->d_counters, s));
   ctx->last_stream = s;
   ctx->has_last_stream = true;
   return ENSF_OK;
@@ -700,6 +703,7 @@ ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream)
   const int use_graph = ctx->opt.use_graph;
   ctx->opt.use_graph = 0;
   const double scales[] = {0.5, 1.0, 2.0};
+  for (int bk : {32, 64})
   for (int gc = 0; gc < kNumGram; ++gc)
     for (int wc = 0; wc < kNumWx; ++wc)
       for (double sc : scales) {
@@ -707,6 +711,7 @@ ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream)
         tc.gram = gc;
         tc.wx = wc;
         tc.split_scale = sc;
+        tc.bk = bk;
         float ms_sum = 0.0f;
         for (int rep = 0; rep < 3 && st == ENSF_OK; ++rep) {
           st = analysis_impl(ctx, probs, s, &tc);  // warm-up on rep 0

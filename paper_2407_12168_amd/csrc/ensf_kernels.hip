@@ -151,29 +151,29 @@ __device__ __forceinline__ float em_step(float z, float s, float xi, const StepS
 // 32x32 accumulator layout (both MFMA kinds): lane l, register r holds
 // row (r/4)*8 + (l/32)*4 + r%4, column l%32.
 
-template <int PREC, int BM, int BN>
+template <int PREC, int BM, int BN, int BK>
 struct TileSmem {
   // FP32 operands are stored k-major ([k][row]) so that a lane's single value per MFMA is
   // read from consecutive addresses; BF16 operands row-major ([row][k]) so a lane reads
   // its 8 consecutive k values as one 16-byte access.
   static constexpr int LDF_A = BM + 4, LDF_B = BN + 4;
-  static constexpr int LDH = kBK + 8;
-  static constexpr int kFp32Bytes = kBK * (LDF_A + LDF_B) * 4;
+  static constexpr int LDH = BK + 8;
+  static constexpr int kFp32Bytes = BK * (LDF_A + LDF_B) * 4;
   static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * 2;
   static constexpr int kBytes = PREC == kFP32 ? kFp32Bytes : kBf16Bytes;
 };
 
-template <int PREC, int WGM, int WGN, int TM, int TN>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&acc)[TM][TN]) {
   constexpr int BM = WGM * TM * 32, BN = WGN * TN * 32;
-  using S = TileSmem<PREC, BM, BN>;
+  using S = TileSmem<PREC, BM, BN, BK>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   if constexpr (PREC == kFP32) {
     const float* sA = reinterpret_cast<const float*>(smem);
-    const float* sB = sA + kBK * S::LDF_A;
+    const float* sB = sA + BK * S::LDF_A;
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 2) {
+    for (int kk = 0; kk < BK; kk += 2) {
       float a[TM], b[TN];
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
@@ -193,7 +193,7 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
     const uint16_t* sBh = sAl + BM * S::LDH;
     const uint16_t* sBl = sBh + BN * S::LDH;
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
+    for (int kk = 0; kk < BK; kk += 16) {
       bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
       const int ko = kk + (lane >> 5) * 8;
 #pragma unroll
@@ -225,16 +225,16 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
 // Operand loaders.  "Kmaj" sources are row-major with k contiguous (Z, X for the Gram,
 // W for W.X); the FP32 W.X B operand X is row-major with the output column contiguous.
 
-// FP32 source, k contiguous, ROWS x kBK tile -> registers (f32x4 per slot).
-template <int ROWS, int NT>
+// FP32 source, k contiguous, ROWS x BK tile -> registers (f32x4 per slot).
+template <int ROWS, int NT, int BK>
 struct F32KmajLoad {
-  static constexpr int kSlots = ROWS * kBK / 4 / NT;
-  static_assert(kSlots * NT * 4 == ROWS * kBK, "tile must split evenly");
+  static constexpr int kSlots = ROWS * BK / 4 / NT;
+  static_assert(kSlots * NT * 4 == ROWS * BK, "tile must split evenly");
   f32x4 v[kSlots];
   __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t row0, int64_t k0) {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
       v[it] = *reinterpret_cast<const f32x4*>(src + (row0 + r) * ld + k0 + c * 4);
     }
   }
@@ -242,7 +242,7 @@ struct F32KmajLoad {
   __device__ __forceinline__ void store_kmajor(float* s, int lds) const {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
       s[(c * 4 + 0) * lds + r] = v[it].x;
       s[(c * 4 + 1) * lds + r] = v[it].y;
       s[(c * 4 + 2) * lds + r] = v[it].z;
@@ -254,7 +254,7 @@ struct F32KmajLoad {
   __device__ __forceinline__ void store_split(uint16_t* sh, uint16_t* sl, int lds) const {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (kBK / 4), c = idx % (kBK / 4);
+      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
       uint16_t h0, h1, h2, h3, l0, l1, l2, l3;
       split_bf16(v[it].x, h0, l0);
       split_bf16(v[it].y, h1, l1);
@@ -267,11 +267,11 @@ struct F32KmajLoad {
   }
 };
 
-// FP32 source with the tile's columns contiguous: kBK rows (k) x COLS -> [k][col] smem.
-template <int COLS, int NT>
+// FP32 source with the tile's columns contiguous: BK rows (k) x COLS -> [k][col] smem.
+template <int COLS, int NT, int BK>
 struct F32NmajLoad {
-  static constexpr int kSlots = COLS * kBK / 4 / NT;
-  static_assert(kSlots * NT * 4 == COLS * kBK, "tile must split evenly");
+  static constexpr int kSlots = COLS * BK / 4 / NT;
+  static_assert(kSlots * NT * 4 == COLS * BK, "tile must split evenly");
   f32x4 v[kSlots];
   __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t k0, int64_t col0) {
 #pragma unroll
@@ -289,11 +289,11 @@ struct F32NmajLoad {
   }
 };
 
-// BF16 source pair (hi, lo), k contiguous, ROWS x kBK tile, 16-byte vectors.
-template <int ROWS, int NT, bool LO>
+// BF16 source pair (hi, lo), k contiguous, ROWS x BK tile, 16-byte vectors.
+template <int ROWS, int NT, bool LO, int BK>
 struct Bf16KmajLoad {
-  static constexpr int kSlots = (ROWS * kBK / 8 + NT - 1) / NT;
-  static constexpr int kVec = ROWS * kBK / 8;
+  static constexpr int kSlots = (ROWS * BK / 8 + NT - 1) / NT;
+  static constexpr int kVec = ROWS * BK / 8;
   u32x4 h[kSlots], l[kSlots];
   __device__ __forceinline__ void load(const uint16_t* srch, const uint16_t* srcl, int64_t ld,
                                        int64_t row0, int64_t k0) {
@@ -301,7 +301,7 @@ struct Bf16KmajLoad {
     for (int it = 0; it < kSlots; ++it) {
       const int idx = threadIdx.x + it * NT;
       if (kVec % NT == 0 || idx < kVec) {
-        const int r = idx / (kBK / 8), c = idx % (kBK / 8);
+        const int r = idx / (BK / 8), c = idx % (BK / 8);
         const int64_t off = (row0 + r) * ld + k0 + c * 8;
         h[it] = *reinterpret_cast<const u32x4*>(srch + off);
         if constexpr (LO) l[it] = *reinterpret_cast<const u32x4*>(srcl + off);
@@ -313,7 +313,7 @@ struct Bf16KmajLoad {
     for (int it = 0; it < kSlots; ++it) {
       const int idx = threadIdx.x + it * NT;
       if (kVec % NT == 0 || idx < kVec) {
-        const int r = idx / (kBK / 8), c = idx % (kBK / 8);
+        const int r = idx / (BK / 8), c = idx % (BK / 8);
         *reinterpret_cast<u32x4*>(sh + r * lds + c * 8) = h[it];
         if constexpr (LO) *reinterpret_cast<u32x4*>(sl + r * lds + c * 8) = l[it];
       }
@@ -324,10 +324,10 @@ struct Bf16KmajLoad {
 // ----------------------------------------------------------------------------------------
 // Gram: part[s][i][j] = sum_{k in chunk s} Z[i][k] X[j][k]
 
-template <int PREC, int WGM, int WGN, int TM, int TN>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
-  using S = TileSmem<PREC, BM, BN>;
+  using S = TileSmem<PREC, BM, BN, BK>;
   __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
@@ -352,29 +352,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
   if constexpr (PREC == kFP32) {
-    F32KmajLoad<BM, NT> la;
-    F32KmajLoad<BN, NT> lb;
+    F32KmajLoad<BM, NT, BK> la;
+    F32KmajLoad<BN, NT, BK> lb;
     float* sA = reinterpret_cast<float*>(smem);
-    float* sB = sA + kBK * S::LDF_A;
+    float* sB = sA + BK * S::LDF_A;
     if (kbeg < kend) {
       la.load(P.Z, P.ldz, m0, kbeg);
       lb.load(P.Xf, P.ldz, n0, kbeg);
     }
-    for (int64_t kb = kbeg; kb < kend; kb += kBK) {
+    for (int64_t kb = kbeg; kb < kend; kb += BK) {
       __syncthreads();
       la.store_kmajor(sA, S::LDF_A);
       lb.store_kmajor(sB, S::LDF_B);
       __syncthreads();
-      if (kb + kBK < kend) {
-        la.load(P.Z, P.ldz, m0, kb + kBK);
-        lb.load(P.Xf, P.ldz, n0, kb + kBK);
+      if (kb + BK < kend) {
+        la.load(P.Z, P.ldz, m0, kb + BK);
+        lb.load(P.Xf, P.ldz, n0, kb + BK);
       }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
     }
   } else {
     constexpr bool LO = PREC == kBF16X3;
-    F32KmajLoad<BM, NT> la;
-    Bf16KmajLoad<BN, NT, LO> lb;
+    F32KmajLoad<BM, NT, BK> la;
+    Bf16KmajLoad<BN, NT, LO, BK> lb;
     uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
     uint16_t* sAl = sAh + BM * S::LDH;
     uint16_t* sBh = sAl + BM * S::LDH;
@@ -383,16 +383,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
       la.load(P.Z, P.ldz, m0, kbeg);
       lb.load(P.Xh, P.Xl, P.ldz, n0, kbeg);
     }
-    for (int64_t kb = kbeg; kb < kend; kb += kBK) {
+    for (int64_t kb = kbeg; kb < kend; kb += BK) {
       __syncthreads();
       la.template store_split<LO>(sAh, sAl, S::LDH);
       lb.store(sBh, sBl, S::LDH);
       __syncthreads();
-      if (kb + kBK < kend) {
-        la.load(P.Z, P.ldz, m0, kb + kBK);
-        lb.load(P.Xh, P.Xl, P.ldz, n0, kb + kBK);
+      if (kb + BK < kend) {
+        la.load(P.Z, P.ldz, m0, kb + BK);
+        lb.load(P.Xh, P.Xl, P.ldz, n0, kb + BK);
       }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
     }
   }
 
@@ -525,11 +525,11 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
 // holds four consecutive components of one particle, i.e. exactly the four normals of one
 // Philox counter, so the epilogue runs from the accumulators without any exchange.
 
-template <int PREC, int WGM, int WGN, int TM, int TN, bool SCORE>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool SCORE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
-  using S = TileSmem<PREC, BE, BP>;
+  using S = TileSmem<PREC, BE, BP, BK>;
   __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
@@ -551,43 +551,43 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 
   const int64_t kend = P.ldn;
   if constexpr (PREC == kFP32) {
-    F32NmajLoad<BE, NT> la;   // X rows (members) x components, components contiguous
-    F32KmajLoad<BP, NT> lb;   // W particles x members, members contiguous
+    F32NmajLoad<BE, NT, BK> la;   // X rows (members) x components, components contiguous
+    F32KmajLoad<BP, NT, BK> lb;   // W particles x members, members contiguous
     float* sA = reinterpret_cast<float*>(smem);
-    float* sB = sA + kBK * S::LDF_A;
+    float* sB = sA + BK * S::LDF_A;
     la.load(P.Xf, P.ldz, 0, e0);
     lb.load(P.W, P.ldn, i0, 0);
-    for (int64_t kb = 0; kb < kend; kb += kBK) {
+    for (int64_t kb = 0; kb < kend; kb += BK) {
       __syncthreads();
       la.store(sA, S::LDF_A);
       lb.store_kmajor(sB, S::LDF_B);
       __syncthreads();
-      if (kb + kBK < kend) {
-        la.load(P.Xf, P.ldz, kb + kBK, e0);
-        lb.load(P.W, P.ldn, i0, kb + kBK);
+      if (kb + BK < kend) {
+        la.load(P.Xf, P.ldz, kb + BK, e0);
+        lb.load(P.W, P.ldn, i0, kb + BK);
       }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
     }
   } else {
     constexpr bool LO = PREC == kBF16X3;
-    Bf16KmajLoad<BE, NT, LO> la;   // X^T components x members
-    Bf16KmajLoad<BP, NT, LO> lb;   // W particles x members
+    Bf16KmajLoad<BE, NT, LO, BK> la;   // X^T components x members
+    Bf16KmajLoad<BP, NT, LO, BK> lb;   // W particles x members
     uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
     uint16_t* sAl = sAh + BE * S::LDH;
     uint16_t* sBh = sAl + BE * S::LDH;
     uint16_t* sBl = sBh + BP * S::LDH;
     la.load(P.XTh, P.XTl, P.ldn, e0, 0);
     lb.load(P.Wh, P.Wl, P.ldn, i0, 0);
-    for (int64_t kb = 0; kb < kend; kb += kBK) {
+    for (int64_t kb = 0; kb < kend; kb += BK) {
       __syncthreads();
       la.store(sAh, sAl, S::LDH);
       lb.store(sBh, sBl, S::LDH);
       __syncthreads();
-      if (kb + kBK < kend) {
-        la.load(P.XTh, P.XTl, P.ldn, e0, kb + kBK);
-        lb.load(P.Wh, P.Wl, P.ldn, i0, kb + kBK);
+      if (kb + BK < kend) {
+        la.load(P.XTh, P.XTl, P.ldn, e0, kb + BK);
+        lb.load(P.Wh, P.Wl, P.ldn, i0, kb + BK);
       }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN>(smem, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
     }
   }
 
@@ -788,11 +788,15 @@ namespace {
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 }
 
-#define ENSF_GRAM_CASE(PR, C, WGM, WGN, TM, TN)                                          \
-  if (prec == PR && cfg == C) {                                                          \
-    hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN>), dim3(g.total), dim3(64 * WGM * WGN), \
-                       0, s, g, step);                                                   \
-    return hipGetLastError();                                                            \
+#define ENSF_GRAM_CASE(PR, C, WGM, WGN, TM, TN)                                              \
+  if (prec == PR && cfg == C) {                                                              \
+    if (bk == 64)                                                                            \
+      hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN, 64>), dim3(g.total),                  \
+                         dim3(64 * WGM * WGN), 0, s, g, step);                               \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN, 32>), dim3(g.total),                  \
+                         dim3(64 * WGM * WGN), 0, s, g, step);                               \
+    return hipGetLastError();                                                                \
   }
 
 #define ENSF_GRAM_ALL(PR)                 \
@@ -801,7 +805,8 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
   ENSF_GRAM_CASE(PR, kGram32, 1, 1, 1, 1)  \
   ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)
 
-hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipStream_t s) {
+hipError_t launch_gram(int prec, int cfg, int bk, const GroupedLaunch& g, int step,
+                       hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
   ENSF_GRAM_ALL(kFP32)
   ENSF_GRAM_ALL(kBF16X3)
@@ -809,14 +814,17 @@ hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipS
   return hipErrorInvalidValue;
 }
 
+#define ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, BKV, SC)                                        \
+  hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, BKV, SC>), dim3(g.total),                   \
+                     dim3(64 * WGM * WGN), 0, s, g, step, nonfinite)
 #define ENSF_WX_CASE(PR, C, WGM, WGN, TM, TN)                                                \
   if (prec == PR && cfg == C) {                                                              \
     if (score_mode)                                                                          \
-      hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, true>), dim3(g.total),                  \
-                         dim3(64 * WGM * WGN), 0, s, g, step, nonfinite);                    \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, true);                                        \
+    else if (bk == 64)                                                                       \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 64, false);                                       \
     else                                                                                     \
-      hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, false>), dim3(g.total),                 \
-                         dim3(64 * WGM * WGN), 0, s, g, step, nonfinite);                    \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, false);                                       \
     return hipGetLastError();                                                                \
   }
 
@@ -828,8 +836,8 @@ hipError_t launch_gram(int prec, int cfg, const GroupedLaunch& g, int step, hipS
   ENSF_WX_CASE(PR, kWx256, 4, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)
 
-hipError_t launch_wx(int prec, int cfg, bool score_mode, const GroupedLaunch& g, int step,
-                     unsigned long long* nonfinite, hipStream_t s) {
+hipError_t launch_wx(int prec, int cfg, int bk, bool score_mode, const GroupedLaunch& g,
+                     int step, unsigned long long* nonfinite, hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
   ENSF_WX_ALL(kFP32)
   ENSF_WX_ALL(kBF16X3)
