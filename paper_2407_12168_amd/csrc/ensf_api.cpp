@@ -47,15 +47,8 @@ struct TileChoice {
 };
 
 struct GraphKey {
-  int prec = -1, gram = -1, wx = -1, np = -1, gtot = -1, rtot = -1, wtot = -1, kmax = -1, ldn = -1;
-  const void* desc = nullptr;
-  const void* pre = nullptr;
-  const void* counters = nullptr;
-  bool operator==(const GraphKey& o) const {
-    return prec == o.prec && gram == o.gram && wx == o.wx && np == o.np && gtot == o.gtot &&
-           rtot == o.rtot && wtot == o.wtot && kmax == o.kmax && ldn == o.ldn && desc == o.desc &&
-           pre == o.pre && counters == o.counters;
-  }
+  std::vector<int64_t> sig;   // launch geometry of every captured kernel
+  bool operator==(const GraphKey& o) const { return sig == o.sig; }
 };
 
 std::string tune_key(int prec, int64_t n, int64_t mp, int64_t d) {
@@ -113,11 +106,22 @@ ensf_status hip_fail(hipError_t e) {
     if (_e != hipSuccess) return hip_fail(_e);      \
   } while (0)
 
-struct Plan {
-  std::vector<ProbDev> desc;
-  std::vector<int32_t> pre_gram, pre_rows, pre_wx;
+// Problems that use the same kernel variant (Gram shape, W.X shape, k-step depth) form a
+// group: one grouped launch per kernel phase and pseudo-step, its problems contiguous in
+// the descriptor table.  The softmax does not depend on tile shapes and covers all rows.
+struct Group {
   TileChoice tiles;
-  std::vector<double> wg_target;
+  int first = 0, count = 0;
+  std::vector<int32_t> pre_gram, pre_wx;
+};
+
+struct Plan {
+  std::vector<ProbDev> desc;        // in group order
+  std::vector<int> order;           // desc[i] describes problem order[i]
+  std::vector<TileChoice> tc;       // per desc entry
+  std::vector<int32_t> pre_rows;
+  std::vector<Group> groups;
+  std::vector<double> wg_target;    // per desc entry
   int kmax = 0;
   int max_ldn = 0;
   size_t ws_needed = 0;
@@ -251,15 +255,7 @@ ensf_status ensure_table(ensf_ctx* c, size_t bytes) {
   return ENSF_OK;
 }
 
-TileChoice choose_tiles(ensf_ctx* c, int prec, const std::vector<ensf_problem>& probs) {
-  // the problem with the most work decides the shapes of a grouped launch
-  size_t best = 0;
-  double work = -1;
-  for (size_t f = 0; f < probs.size(); ++f) {
-    const double w = (double)probs[f].n_members * probs[f].n_particles * probs[f].dim;
-    if (w > work) { work = w; best = f; }
-  }
-  const ensf_problem& p = probs[best];
+TileChoice tiles_for(ensf_ctx* c, int prec, const ensf_problem& p) {
   auto it = c->tune.find(tune_key(prec, p.n_members, p.n_particles, p.dim));
   if (it != c->tune.end()) return it->second;
   return heuristic_tiles(p.n_members, p.n_particles);
@@ -268,31 +264,61 @@ TileChoice choose_tiles(ensf_ctx* c, int prec, const std::vector<ensf_problem>& 
 ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan,
                        const TileChoice* force) {
   const int prec = c->opt.precision;
-  plan.tiles = force ? *force : choose_tiles(c, prec, probs);
   const int np = (int)probs.size();
+  std::vector<TileChoice> tc(np);
+  std::vector<int> gid(np);
+  plan.groups.clear();
+  for (int f = 0; f < np; ++f) {
+    tc[f] = force ? *force : tiles_for(c, prec, probs[f]);
+    int g = 0;
+    for (; g < (int)plan.groups.size(); ++g) {
+      const TileChoice& t = plan.groups[g].tiles;
+      if (t.gram == tc[f].gram && t.wx == tc[f].wx && t.bk == tc[f].bk) break;
+    }
+    if (g == (int)plan.groups.size()) {
+      plan.groups.emplace_back();
+      plan.groups.back().tiles = tc[f];
+    }
+    gid[f] = g;
+  }
+  plan.order.clear();
+  for (int g = 0; g < (int)plan.groups.size(); ++g) {
+    plan.groups[g].first = (int)plan.order.size();
+    for (int f = 0; f < np; ++f)
+      if (gid[f] == g) plan.order.push_back(f);
+    plan.groups[g].count = (int)plan.order.size() - plan.groups[g].first;
+    plan.groups[g].pre_gram.assign(plan.groups[g].count + 1, 0);
+    plan.groups[g].pre_wx.assign(plan.groups[g].count + 1, 0);
+  }
+  plan.tc.resize(np);
   plan.desc.resize(np);
-  plan.pre_gram.assign(np + 1, 0);
   plan.pre_rows.assign(np + 1, 0);
-  plan.pre_wx.assign(np + 1, 0);
-  size_t off = 0;
-  plan.kmax = 0;
-  plan.max_ldn = 0;
   plan.wg_target.assign(np, 1024.0);
   double total = 0;
   for (const auto& p : probs) total += (double)p.n_members * p.n_particles * p.dim;
-  for (int f = 0; f < np; ++f)
-    plan.wg_target[f] = std::max(8.0, 1024.0 * (double)probs[f].n_members *
-                                          probs[f].n_particles * probs[f].dim / total);
-  for (int f = 0; f < np; ++f) {
-    ProbDev& P = plan.desc[f];
-    off = layout_problem(P, probs[f], prec, plan.tiles, c->opt.obs_op, c->opt.eps_alpha,
-                         plan.wg_target[f], off, nullptr);
-    const int64_t g = (int64_t)P.gram_tm * P.gram_tn * P.S;
-    const int64_t w = (int64_t)P.wx_tp * P.wx_te;
-    if (plan.pre_gram[f] + g > INT32_MAX || plan.pre_wx[f] + w > INT32_MAX) return ENSF_EINVAL;
-    plan.pre_gram[f + 1] = plan.pre_gram[f] + (int32_t)g;
-    plan.pre_rows[f + 1] = plan.pre_rows[f] + P.Mp;
-    plan.pre_wx[f + 1] = plan.pre_wx[f] + (int32_t)w;
+  size_t off = 0;
+  plan.kmax = 0;
+  plan.max_ldn = 0;
+  for (int i = 0; i < np; ++i) {
+    const int f = plan.order[i];
+    const ensf_problem& p = probs[f];
+    plan.tc[i] = tc[f];
+    // this problem's share of ~1024 workgroups per Gram launch
+    plan.wg_target[i] =
+        std::max(8.0, 1024.0 * (double)p.n_members * p.n_particles * p.dim / total);
+    ProbDev& P = plan.desc[i];
+    off = layout_problem(P, p, prec, plan.tc[i], c->opt.obs_op, c->opt.eps_alpha,
+                         plan.wg_target[i], off, nullptr);
+    Group& G = plan.groups[gid[f]];
+    const int j = i - G.first;
+    const int64_t gw = (int64_t)P.gram_tm * P.gram_tn * P.S;
+    const int64_t ww = (int64_t)P.wx_tp * P.wx_te;
+    if (G.pre_gram[j] + gw > INT32_MAX || G.pre_wx[j] + ww > INT32_MAX ||
+        plan.pre_rows[i] + (int64_t)P.Mp > INT32_MAX)
+      return ENSF_EINVAL;
+    G.pre_gram[j + 1] = G.pre_gram[j] + (int32_t)gw;
+    G.pre_wx[j + 1] = G.pre_wx[j] + (int32_t)ww;
+    plan.pre_rows[i + 1] = plan.pre_rows[i] + P.Mp;
     plan.kmax = std::max(plan.kmax, P.K);
     plan.max_ldn = std::max(plan.max_ldn, P.ldn);
   }
@@ -303,36 +329,56 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
 // Second pass: real pointers once the workspace exists.
 void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) {
   size_t off = 0;
-  for (size_t f = 0; f < probs.size(); ++f)
-    off = layout_problem(plan.desc[f], probs[f], c->opt.precision, plan.tiles, c->opt.obs_op,
-                         c->opt.eps_alpha, plan.wg_target[f], off, c->ws);
+  for (size_t i = 0; i < plan.desc.size(); ++i)
+    off = layout_problem(plan.desc[i], probs[plan.order[i]], c->opt.precision, plan.tc[i],
+                         c->opt.obs_op, c->opt.eps_alpha, plan.wg_target[i], off, c->ws);
 }
 
 struct Uploaded {
-  GroupedLaunch gram, rows, wx;
+  GroupedLaunch rows;
+  std::vector<GroupedLaunch> gram, wx;   // one per group
 };
 
 ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& u) {
   const int np = (int)plan.desc.size();
-  const size_t desc_bytes = round_up(sizeof(ProbDev) * np, 256);
-  const size_t pre_bytes = round_up(sizeof(int32_t) * (np + 1), 256);
-  ensf_status st = ensure_table(c, desc_bytes + 3 * pre_bytes);
+  auto al = [](size_t v) { return (size_t)round_up((int64_t)v, 256); };
+  size_t bytes = al(sizeof(ProbDev) * np) + al(sizeof(int32_t) * (np + 1));
+  for (const Group& G : plan.groups) bytes += 2 * al(sizeof(int32_t) * (G.count + 1));
+  ensf_status st = ensure_table(c, bytes);
   if (st != ENSF_OK) return st;
   if (c->tab_event_pending) HIP_TRY(hipEventSynchronize(c->tab_event));
-  memcpy(c->h_tab, plan.desc.data(), sizeof(ProbDev) * np);
-  memcpy(c->h_tab + desc_bytes, plan.pre_gram.data(), sizeof(int32_t) * (np + 1));
-  memcpy(c->h_tab + desc_bytes + pre_bytes, plan.pre_rows.data(), sizeof(int32_t) * (np + 1));
-  memcpy(c->h_tab + desc_bytes + 2 * pre_bytes, plan.pre_wx.data(), sizeof(int32_t) * (np + 1));
-  HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, desc_bytes + 3 * pre_bytes, hipMemcpyHostToDevice, s));
+  size_t off = 0;
+  auto put = [&](const void* src, size_t n) {
+    memcpy(c->h_tab + off, src, n);
+    const size_t at = off;
+    off += al(n);
+    return at;
+  };
+  const size_t o_desc = put(plan.desc.data(), sizeof(ProbDev) * np);
+  const size_t o_rows = put(plan.pre_rows.data(), sizeof(int32_t) * (np + 1));
+  std::vector<std::pair<size_t, size_t>> o_grp;
+  for (const Group& G : plan.groups) {
+    const size_t a = put(G.pre_gram.data(), sizeof(int32_t) * (G.count + 1));
+    const size_t b = put(G.pre_wx.data(), sizeof(int32_t) * (G.count + 1));
+    o_grp.emplace_back(a, b);
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, off, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(c->tab_event, s));
   c->tab_event_pending = true;
-  const ProbDev* d = reinterpret_cast<const ProbDev*>(c->d_tab);
-  const int32_t* pg = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes);
-  const int32_t* pr = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes + pre_bytes);
-  const int32_t* pw = reinterpret_cast<const int32_t*>(c->d_tab + desc_bytes + 2 * pre_bytes);
-  u.gram = GroupedLaunch{d, pg, np, plan.pre_gram[np]};
-  u.rows = GroupedLaunch{d, pr, np, plan.pre_rows[np]};
-  u.wx = GroupedLaunch{d, pw, np, plan.pre_wx[np]};
+  const ProbDev* d = reinterpret_cast<const ProbDev*>(c->d_tab + o_desc);
+  u.rows = GroupedLaunch{d, reinterpret_cast<const int32_t*>(c->d_tab + o_rows), np,
+                         plan.pre_rows[np]};
+  u.gram.clear();
+  u.wx.clear();
+  for (size_t g = 0; g < plan.groups.size(); ++g) {
+    const Group& G = plan.groups[g];
+    u.gram.push_back(GroupedLaunch{d + G.first,
+                                   reinterpret_cast<const int32_t*>(c->d_tab + o_grp[g].first),
+                                   G.count, G.pre_gram[G.count]});
+    u.wx.push_back(GroupedLaunch{d + G.first,
+                                 reinterpret_cast<const int32_t*>(c->d_tab + o_grp[g].second),
+                                 G.count, G.pre_wx[G.count]});
+  }
   return ENSF_OK;
 }
 
@@ -376,12 +422,27 @@ ensf_status ensure_softmax_smem(ensf_ctx* c, int max_ldn) {
   return ENSF_OK;
 }
 
+ensf_status launch_grams(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k, hipStream_t s) {
+  for (size_t g = 0; g < plan.groups.size(); ++g)
+    HIP_TRY(launch_gram(c->opt.precision, plan.groups[g].tiles.gram, plan.groups[g].tiles.bk,
+                        u.gram[g], k, s));
+  return ENSF_OK;
+}
+
+ensf_status launch_wxs(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k, hipStream_t s) {
+  for (size_t g = 0; g < plan.groups.size(); ++g)
+    HIP_TRY(launch_wx(c->opt.precision, plan.groups[g].tiles.wx, plan.groups[g].tiles.bk, false,
+                      u.wx[g], k, c->d_counters, s));
+  return ENSF_OK;
+}
+
 ensf_status enqueue_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStream_t s) {
-  const int prec = c->opt.precision;
   for (int k = 0; k < plan.kmax; ++k) {
-    HIP_TRY(launch_gram(prec, plan.tiles.gram, plan.tiles.bk, u.gram, k, s));
-    HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
-    HIP_TRY(launch_wx(prec, plan.tiles.wx, plan.tiles.bk, false, u.wx, k, c->d_counters, s));
+    ensf_status st = launch_grams(c, plan, u, k, s);
+    if (st != ENSF_OK) return st;
+    HIP_TRY(launch_softmax(c->opt.precision, u.rows, k, plan.max_ldn, s));
+    st = launch_wxs(c, plan, u, k, s);
+    if (st != ENSF_OK) return st;
   }
   return ENSF_OK;
 }
@@ -412,16 +473,17 @@ ensf_status enqueue_steps_profiled(ensf_ctx* c, const Plan& plan, const Uploaded
     HIP_TRY(hipEventCreate(&e));
     c->events.push_back(e);
   }
-  const int prec = c->opt.precision;
   const size_t first = c->events_used;
   for (int k = 0; k < plan.kmax; ++k) {
     hipEvent_t* ev = &c->events[first + 4 * k];
     HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_gram(prec, plan.tiles.gram, plan.tiles.bk, u.gram, k, s));
+    ensf_status st = launch_grams(c, plan, u, k, s);
+    if (st != ENSF_OK) return st;
     HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_softmax(prec, u.rows, k, plan.max_ldn, s));
+    HIP_TRY(launch_softmax(c->opt.precision, u.rows, k, plan.max_ldn, s));
     HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_wx(prec, plan.tiles.wx, plan.tiles.bk, false, u.wx, k, c->d_counters, s));
+    st = launch_wxs(c, plan, u, k, s);
+    if (st != ENSF_OK) return st;
     HIP_TRY(hipEventRecord(ev[3], s));
   }
   c->events_used = need;
@@ -439,18 +501,18 @@ ensf_status run_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStrea
   }
   if (!c->opt.use_graph) return enqueue_steps(c, plan, u, s);
   GraphKey key;
-  key.prec = c->opt.precision;
-  key.gram = plan.tiles.gram;
-  key.wx = plan.tiles.wx;
-  key.np = u.gram.np;
-  key.gtot = u.gram.total;
-  key.rtot = u.rows.total;
-  key.wtot = u.wx.total;
-  key.kmax = plan.kmax;
-  key.ldn = plan.max_ldn;
-  key.desc = u.gram.desc;
-  key.pre = u.gram.pre;
-  key.counters = c->d_counters;
+  auto addp = [&](const void* p) { key.sig.push_back((int64_t)reinterpret_cast<uintptr_t>(p)); };
+  key.sig = {c->opt.precision, plan.kmax, plan.max_ldn, u.rows.np, u.rows.total};
+  addp(u.rows.desc);
+  addp(u.rows.pre);
+  addp(c->d_counters);
+  for (size_t g = 0; g < plan.groups.size(); ++g) {
+    const TileChoice& t = plan.groups[g].tiles;
+    key.sig.insert(key.sig.end(), {t.gram, t.wx, t.bk, u.gram[g].np, u.gram[g].total, u.wx[g].total});
+    addp(u.gram[g].desc);
+    addp(u.gram[g].pre);
+    addp(u.wx[g].pre);
+  }
   if (!(c->gexec && key == c->gkey)) {
     if (c->gexec) {
       HIP_TRY(hipGraphExecDestroy(c->gexec));
@@ -648,9 +710,10 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   st = prep_problem(ctx, P, true, s);
   if (st != ENSF_OK) return st;
   const int prec = ctx->opt.precision;
-  HIP_TRY(launch_gram(prec, plan.tiles.gram, 32, u.gram, -1, s));
+  const TileChoice& tiles = plan.groups[0].tiles;
+  HIP_TRY(launch_gram(prec, tiles.gram, tiles.bk, u.gram[0], -1, s));
   HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
-  HIP_TRY(launch_wx(prec, plan.tiles.wx, 32, true, u.wx, -1, ctx->d_counters, s));
+  HIP_TRY(launch_wx(prec, tiles.wx, 32, true, u.wx[0], -1, ctx->d_counters, s));
   ctx->last_stream = s;
   ctx->has_last_stream = true;
   return ENSF_OK;
