@@ -222,6 +222,45 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
   }
 }
 
+// The k loop of a tile.  load(kb) fetches the k-step starting at kb from global memory
+// into registers, store(stage) writes those registers into one LDS stage.  With PP (two
+// stages fit) the loop ping-pongs between two stages: one barrier per k-step, and the LDS
+// store of step k+1 overlaps the other waves' MFMAs on step k while the global loads of
+// step k+2 are in flight.  Otherwise one stage is refilled between two barriers.
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool PP, class Load, class Store>
+__device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t kend, Load&& load,
+                                            Store&& store, f32x16_t (&acc)[TM][TN]) {
+  constexpr int STAGE = TileSmem<PREC, WGM * TM * 32, WGN * TN * 32, BK>::kBytes;
+  if (kbeg >= kend) return;
+  load(kbeg);
+  if constexpr (PP) {
+    store(smem);
+    if (kbeg + BK < kend) load(kbeg + BK);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t kb = kbeg; kb < kend; kb += BK) {
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem + cur * STAGE, acc);
+      if (kb + BK < kend) {
+        store(smem + (cur ^ 1) * STAGE);
+        if (kb + 2 * BK < kend) load(kb + 2 * BK);
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    for (int64_t kb = kbeg; kb < kend; kb += BK) {
+      __syncthreads();
+      store(smem);
+      __syncthreads();
+      if (kb + BK < kend) load(kb + BK);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
+    }
+  }
+}
+
+// Two LDS stages are used when they fit in this budget (leaves room for 1-2 workgroups).
+constexpr int kPingPongBytes = 96 * 1024;
+
 // Operand loaders.  "Kmaj" sources are row-major with k contiguous (Z, X for the Gram,
 // W for W.X); the FP32 W.X B operand X is row-major with the output column contiguous.
 
@@ -328,7 +367,8 @@ template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
   using S = TileSmem<PREC, BM, BN, BK>;
-  __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
+  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
   const int f = find_problem(g.pre, g.np, tile);
@@ -354,46 +394,36 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
   if constexpr (PREC == kFP32) {
     F32KmajLoad<BM, NT, BK> la;
     F32KmajLoad<BN, NT, BK> lb;
-    float* sA = reinterpret_cast<float*>(smem);
-    float* sB = sA + BK * S::LDF_A;
-    if (kbeg < kend) {
-      la.load(P.Z, P.ldz, m0, kbeg);
-      lb.load(P.Xf, P.ldz, n0, kbeg);
-    }
-    for (int64_t kb = kbeg; kb < kend; kb += BK) {
-      __syncthreads();
-      la.store_kmajor(sA, S::LDF_A);
-      lb.store_kmajor(sB, S::LDF_B);
-      __syncthreads();
-      if (kb + BK < kend) {
-        la.load(P.Z, P.ldz, m0, kb + BK);
-        lb.load(P.Xf, P.ldz, n0, kb + BK);
-      }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
-    }
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+        smem, kbeg, kend,
+        [&](int64_t kb) {
+          la.load(P.Z, P.ldz, m0, kb);
+          lb.load(P.Xf, P.ldz, n0, kb);
+        },
+        [&](char* st) {
+          float* sA = reinterpret_cast<float*>(st);
+          la.store_kmajor(sA, S::LDF_A);
+          lb.store_kmajor(sA + BK * S::LDF_A, S::LDF_B);
+        },
+        acc);
   } else {
     constexpr bool LO = PREC == kBF16X3;
     F32KmajLoad<BM, NT, BK> la;
     Bf16KmajLoad<BN, NT, LO, BK> lb;
-    uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* sAl = sAh + BM * S::LDH;
-    uint16_t* sBh = sAl + BM * S::LDH;
-    uint16_t* sBl = sBh + BN * S::LDH;
-    if (kbeg < kend) {
-      la.load(P.Z, P.ldz, m0, kbeg);
-      lb.load(P.Xh, P.Xl, P.ldz, n0, kbeg);
-    }
-    for (int64_t kb = kbeg; kb < kend; kb += BK) {
-      __syncthreads();
-      la.template store_split<LO>(sAh, sAl, S::LDH);
-      lb.store(sBh, sBl, S::LDH);
-      __syncthreads();
-      if (kb + BK < kend) {
-        la.load(P.Z, P.ldz, m0, kb + BK);
-        lb.load(P.Xh, P.Xl, P.ldz, n0, kb + BK);
-      }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
-    }
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+        smem, kbeg, kend,
+        [&](int64_t kb) {
+          la.load(P.Z, P.ldz, m0, kb);
+          lb.load(P.Xh, P.Xl, P.ldz, n0, kb);
+        },
+        [&](char* st) {
+          uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
+          uint16_t* sAl = sAh + BM * S::LDH;
+          uint16_t* sBh = sAl + BM * S::LDH;
+          la.template store_split<LO>(sAh, sAl, S::LDH);
+          lb.store(sBh, sBh + BN * S::LDH, S::LDH);
+        },
+        acc);
   }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -530,7 +560,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
   using S = TileSmem<PREC, BE, BP, BK>;
-  __shared__ __attribute__((aligned(16))) char smem[S::kBytes];
+  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
   const int f = find_problem(g.pre, g.np, tile);
@@ -549,46 +580,39 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  const int64_t kend = P.ldn;
   if constexpr (PREC == kFP32) {
     F32NmajLoad<BE, NT, BK> la;   // X rows (members) x components, components contiguous
     F32KmajLoad<BP, NT, BK> lb;   // W particles x members, members contiguous
-    float* sA = reinterpret_cast<float*>(smem);
-    float* sB = sA + BK * S::LDF_A;
-    la.load(P.Xf, P.ldz, 0, e0);
-    lb.load(P.W, P.ldn, i0, 0);
-    for (int64_t kb = 0; kb < kend; kb += BK) {
-      __syncthreads();
-      la.store(sA, S::LDF_A);
-      lb.store_kmajor(sB, S::LDF_B);
-      __syncthreads();
-      if (kb + BK < kend) {
-        la.load(P.Xf, P.ldz, kb + BK, e0);
-        lb.load(P.W, P.ldn, i0, kb + BK);
-      }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
-    }
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+        smem, 0, P.ldn,
+        [&](int64_t kb) {
+          la.load(P.Xf, P.ldz, kb, e0);
+          lb.load(P.W, P.ldn, i0, kb);
+        },
+        [&](char* st) {
+          float* sA = reinterpret_cast<float*>(st);
+          la.store(sA, S::LDF_A);
+          lb.store_kmajor(sA + BK * S::LDF_A, S::LDF_B);
+        },
+        acc);
   } else {
     constexpr bool LO = PREC == kBF16X3;
     Bf16KmajLoad<BE, NT, LO, BK> la;   // X^T components x members
     Bf16KmajLoad<BP, NT, LO, BK> lb;   // W particles x members
-    uint16_t* sAh = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* sAl = sAh + BE * S::LDH;
-    uint16_t* sBh = sAl + BE * S::LDH;
-    uint16_t* sBl = sBh + BP * S::LDH;
-    la.load(P.XTh, P.XTl, P.ldn, e0, 0);
-    lb.load(P.Wh, P.Wl, P.ldn, i0, 0);
-    for (int64_t kb = 0; kb < kend; kb += BK) {
-      __syncthreads();
-      la.store(sAh, sAl, S::LDH);
-      lb.store(sBh, sBl, S::LDH);
-      __syncthreads();
-      if (kb + BK < kend) {
-        la.load(P.XTh, P.XTl, P.ldn, e0, kb + BK);
-        lb.load(P.Wh, P.Wl, P.ldn, i0, kb + BK);
-      }
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
-    }
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+        smem, 0, P.ldn,
+        [&](int64_t kb) {
+          la.load(P.XTh, P.XTl, P.ldn, e0, kb);
+          lb.load(P.Wh, P.Wl, P.ldn, i0, kb);
+        },
+        [&](char* st) {
+          uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
+          uint16_t* sAl = sAh + BE * S::LDH;
+          uint16_t* sBh = sAl + BE * S::LDH;
+          la.store(sAh, sAl, S::LDH);
+          lb.store(sBh, sBh + BP * S::LDH, S::LDH);
+        },
+        acc);
   }
 
   const StepScalars sc = step_scalars(step_time(P, step), P.eps, P.K);
