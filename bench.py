@@ -12,7 +12,7 @@ workload is reported alongside.  The dominant kernel's roofline point comes from
 recorded around every launch on the launch stream (ensf_profile_phases).  The CPU baseline
 is the FP64 oracle on a bounded particle subset, scaled to the full analysis.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|1|3] [--precision fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|1|3|4|5] [--precision fp32]
 """
 import argparse
 import json
@@ -33,7 +33,64 @@ WORKLOAD = {
     4: "64 independent EnSF filters in one batched call: d uniform in {2x64x64, 2x128x128, "
        "2x256x256}, N=M_p uniform in 32..512, arctan obs of 10-100% of components, "
        "sigma_o=0.05, K=100",
+    5: "learned-forecast assimilation cycle: 50 cycles on 2x128x128 SQG states, N=M_p=512, "
+       "forecast by a 6-layer 3x3 conv net (64 channels) trained on 2000 SQG pairs, "
+       "split-BF16 EnSF analysis of obs every 4th grid point (sigma_o=0.05, K=400)",
 }
+
+
+def run_cycle_bench(a):
+    """Config 5: train the surrogate, cycle with it, with the SQG model and with no forecast
+    model; the metric is the analyses' member-dim updates per second."""
+    import numpy as np
+    import torch
+
+    from paper_2407_12168_amd import cycle
+    dev = torch.device("cuda:0")
+    cfg = cycle.CycleConfig(cycles=a.cycles)
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    x, y = cycle.training_pairs(2000, cfg, dev)
+    xv, yv = cycle.training_pairs(64, cfg, dev, seed=cfg.seed + 77)
+    log(f"2000 SQG training pairs in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    sur, hist = cycle.train_surrogate(x, y, epochs=a.epochs, batch=32, lr=1e-3, val=(xv, yv),
+                                      log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    n_steps_train = a.epochs * (2000 // 32)
+    train_flops = 3 * 4.91e9 * 32 * n_steps_train
+    del x, y
+    runs = {}
+    for name in ("conv", "sqg", "persistence"):
+        runs[name] = cycle.run_cycle(cfg, name, surrogate=sur if name == "conv" else None,
+                                     dev=dev, log=log)
+    sur.destroy()
+    conv = runs["conv"]
+    ndk = cfg.members * 2 * cfg.grid * cfg.grid * cfg.pseudo_steps
+    ms = 1e3 * float(np.mean(conv.analysis_s))
+    summary = {n: {"rmse_analysis_mean": float(np.mean(r.rmse[5:])),
+                   "rmse_forecast_mean": float(np.mean(r.rmse_forecast[5:])),
+                   "forecast_ms_per_cycle": 1e3 * float(np.mean(r.forecast_s)),
+                   "analysis_ms_per_cycle": 1e3 * float(np.mean(r.analysis_s)),
+                   "rmse_analysis": [round(v, 5) for v in r.rmse]}
+               for n, r in runs.items()}
+    line = {
+        "metric": "EnSF member-dim updates/s (N*d*K/s)",
+        "value": ndk / (ms * 1e-3), "unit": "member-dim updates/s",
+        "n_gpus": 1, "steps": cfg.cycles, "warmup": 0, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD[5], "precision": "bf16x3", "members": cfg.members,
+                   "dim": 2 * cfg.grid * cfg.grid, "pseudo_steps": cfg.pseudo_steps,
+                   "obs": int(2 * (cfg.grid // cfg.obs_stride) ** 2)},
+        "cycle": summary,
+        "surrogate_training": {"seconds": train_s, "steps": n_steps_train,
+                               "tflops_per_s": train_flops / train_s / 1e12,
+                               "final_val_mse": hist[-1].get("val_mse"),
+                               "persistence_val_mse": float(torch.mean((xv - yv) ** 2))},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def run_form(probs, precision, steps, warmup, dev):
@@ -128,7 +185,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--cycles", type=int, default=50, help="config 5: assimilation cycles")
+    ap.add_argument("--epochs", type=int, default=30, help="config 5: surrogate epochs")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16x3", "bf16"))
     ap.add_argument("--other-form", default=None,
                     help="second precision reported alongside (default: the other of fp32/bf16x3)")
@@ -139,6 +198,10 @@ def main():
         print("bench.py: this build runs on one GPU only (the analysis shards over particles or "
               "filters; no multi-GPU path is built).", file=sys.stderr)
         sys.exit(2)
+
+    if a.config == 5:
+        run_cycle_bench(a)
+        return
 
     import torch
 
