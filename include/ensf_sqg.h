@@ -11,8 +11,10 @@
  *     psi_0 = -theta_0/(K tanh K) + theta_1/(K sinh K),
  *     psi_1 = -theta_0/(K sinh K) + theta_1/(K tanh K),
  * with the nonlinear term computed on the grid and transformed back with the 2/3 rule on
- * both wavenumber components, classical RK4 in time, and hyperdiffusion applied exactly
- * after each step: theta_hat *= exp(-dt/efold * (K / (2/3 K_max))^order).
+ * both wavenumber components, classical RK4 in time, and two linear damping terms applied
+ * exactly after each step: hyperdiffusion and a thermal relaxation of theta toward the
+ * basic state with time scale relax_time (it lets the turbulence equilibrate):
+ *     theta_hat *= exp(-dt/efold * (K / (2/3 K_max))^order - dt/relax_time).
  * The FFTs are hipFFT (D2Z / Z2D); everything else runs in this library's kernels.
  *
  * States are (batch, 2, n, n) row-major (component e = level*n*n + iy*n + ix), the layout
@@ -33,11 +35,11 @@ extern "C" {
 typedef struct ensf_sqg ensf_sqg;
 
 /* n: even grid size >= 8; lx > 0; dt > 0; diff_order >= 2; diff_efold > 0 (e-folding time
-   of the highest retained wavenumber, INFINITY = no diffusion); max_batch >= 1 states per
-   internal chunk.  device: HIP ordinal. */
+   of the highest retained wavenumber, INFINITY = no diffusion); relax_time > 0 (INFINITY =
+   no relaxation); max_batch >= 1 states per internal chunk.  device: HIP ordinal. */
 ensf_status ensf_sqg_create(int32_t n, double lx, double shear, double dt, int32_t diff_order,
-                            double diff_efold, int32_t max_batch, int32_t device,
-                            ensf_sqg** out);
+                            double diff_efold, double relax_time, int32_t max_batch,
+                            int32_t device, ensf_sqg** out);
 
 /* Advances `batch` FP64 states by n_steps time steps (d_out may equal d_in). */
 ensf_status ensf_sqg_run(ensf_sqg* s, const double* d_in, double* d_out, int32_t batch,

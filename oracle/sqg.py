@@ -16,8 +16,10 @@ Equations (theta_i on level i, psi_i the boundary streamfunctions):
 with the zero-PV inversion (wavenumber magnitude K):
     psi_0 = -theta_0 / (K tanh K) + theta_1 / (K sinh K)
     psi_1 = -theta_0 / (K sinh K) + theta_1 / (K tanh K)
-and D a hyperdiffusion of order 2p applied exactly over each step (integrating factor):
-    theta_hat <- theta_hat * exp(-dt * nu * (K / K_max)^(2p)).
+and D a hyperdiffusion of order 2p plus a thermal relaxation toward the basic state with
+time scale tau (which lets the turbulence equilibrate), both linear and applied exactly
+over each step:
+    theta_hat <- theta_hat * exp(-dt * nu * (K / K_max)^(2p) - dt / tau).
 State layout: (2, n, n) float64, level-major (component e = level*n*n + iy*n + ix).
 """
 import numpy as np
@@ -25,7 +27,7 @@ import numpy as np
 
 class SQG:
     def __init__(self, n=128, lx=20.0, shear=1.0, dt=0.025, diff_order=8, diff_efold=None,
-                 dealias=True):
+                 dealias=True, relax_time=np.inf):
         self.n, self.lx, self.shear, self.dt = n, lx, shear, dt
         k1 = 2.0 * np.pi / lx
         kx = np.fft.rfftfreq(n, 1.0 / n) * k1
@@ -45,6 +47,8 @@ class SQG:
         efold = diff_efold if diff_efold is not None else 10.0 * dt
         self.hyper = (np.exp(-dt / efold * (K / (2.0 / 3.0 * kmax)) ** diff_order)
                       if diff_efold != np.inf else np.ones_like(K))
+        # thermal relaxation of theta toward the basic state (linear damping, exact per step)
+        self.hyper = self.hyper * np.exp(-dt / relax_time)
         self.U = np.array([-0.5 * shear, 0.5 * shear])
 
     # spectral helpers ---------------------------------------------------------------

@@ -14,7 +14,7 @@ namespace {
 
 struct SqgParams {
   int n, nh, batch;
-  double k1, shear, dt, efold, kcut;
+  double k1, shear, dt, efold, kcut, relax;
   int order;
 };
 
@@ -91,7 +91,8 @@ __global__ void k_sqg_stage(SqgParams p, const double2* __restrict__ advh, doubl
   } else {
     const double2 c = kacc[idx];
     const double K = sqrt(kx * kx + ky * ky);
-    const double hyper = isinf(p.efold) ? 1.0 : exp(-p.dt / p.efold * pow(K / p.kcut, (double)p.order));
+    const double diff = isinf(p.efold) ? 0.0 : p.dt / p.efold * pow(K / p.kcut, (double)p.order);
+    const double hyper = exp(-diff) * exp(-p.dt / p.relax);
     const double2 nt = make_double2((t.x + p.dt / 6.0 * (c.x + k.x)) * hyper,
                                     (t.y + p.dt / 6.0 * (c.y + k.y)) * hyper);
     th[idx] = nt;
@@ -148,7 +149,7 @@ ensf_status fail(hipError_t e) {
 
 struct ensf_sqg {
   int n = 0, nh = 0, max_batch = 0, device = 0, order = 8;
-  double lx = 20.0, shear = 1.0, dt = 0.025, efold = 0.25;
+  double lx = 20.0, shear = 1.0, dt = 0.025, efold = 0.25, relax = INFINITY;
   double2 *th = nullptr, *ts = nullptr, *kacc = nullptr, *d4 = nullptr, *advh = nullptr;
   double *r4 = nullptr, *adv = nullptr, *state = nullptr;
   std::map<int, hipfftHandle> z2d, d2z;   // plans keyed by the number of fields
@@ -182,6 +183,7 @@ SqgParams params(const ensf_sqg* s, int batch) {
   p.efold = s->efold;
   p.kcut = 2.0 / 3.0 * p.k1 * (s->n / 2);
   p.order = s->order;
+  p.relax = s->relax;
   return p;
 }
 
@@ -246,12 +248,12 @@ ensf_status run_any(ensf_sqg* s, const T* d_in, T* d_out, int batch, int n_steps
 extern "C" {
 
 ensf_status ensf_sqg_create(int32_t n, double lx, double shear, double dt, int32_t diff_order,
-                            double diff_efold, int32_t max_batch, int32_t device,
-                            ensf_sqg** out) {
+                            double diff_efold, double relax_time, int32_t max_batch,
+                            int32_t device, ensf_sqg** out) {
   if (!out) return ENSF_EINVAL;
   *out = nullptr;
   if (n < 8 || n % 2 || !(lx > 0) || !(dt > 0) || diff_order < 2 || !(diff_efold > 0) ||
-      max_batch < 1)
+      !(relax_time > 0) || max_batch < 1)
     return ENSF_EINVAL;
   ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(device));
@@ -263,6 +265,7 @@ ensf_status ensf_sqg_create(int32_t n, double lx, double shear, double dt, int32
   s->dt = dt;
   s->order = diff_order;
   s->efold = diff_efold;
+  s->relax = relax_time;
   s->max_batch = max_batch;
   s->device = device;
   const size_t spec = (size_t)max_batch * 2 * n * s->nh * sizeof(double2);

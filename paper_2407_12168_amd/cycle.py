@@ -24,9 +24,10 @@ class CycleConfig:
     precision: str = "bf16x3"
     spread_relax: float = 1.0    # relax the analysis spread to the prior spread
     sqg_dt: float = 0.025
+    relax_time: float = 5.0      # SQG thermal relaxation (lets the turbulence equilibrate)
     steps_per_cycle: int = 20    # forecast length between analyses (0.5 time units)
-    spinup_steps: int = 400
-    init_spread: float = 0.5     # initial ensemble perturbation std relative to the truth
+    spinup_steps: int = 800
+    trajectories: int = 16       # independent SQG runs the climatological states come from
     seed: int = 2412
     filter_seed: int = 12173
 
@@ -35,6 +36,8 @@ class CycleConfig:
 class CycleResult:
     rmse: list = field(default_factory=list)          # analysis mean vs truth, per cycle
     rmse_forecast: list = field(default_factory=list)  # forecast mean vs truth, per cycle
+    rmse_obs: list = field(default_factory=list)       # analysis mean, observed components
+    rmse_forecast_obs: list = field(default_factory=list)  # forecast mean, observed components
     spread: list = field(default_factory=list)
     forecast_s: list = field(default_factory=list)
     analysis_s: list = field(default_factory=list)
@@ -46,16 +49,27 @@ def obs_indices(grid, stride):
     return np.sort((lv * grid * grid + iy * grid + ix).reshape(-1)).astype(np.int32)
 
 
-def spun_up_states(sqg, count, cfg, rng, dev):
-    """`count` SQG states: red-spectrum random fields integrated for spinup_steps."""
+def sqg_model(cfg, max_batch):
+    from .sqg import SQGModel
+    return SQGModel(n=cfg.grid, dt=cfg.sqg_dt, relax_time=cfg.relax_time, max_batch=max_batch)
+
+
+def climate_trajectories(sqg, cfg, samples, rng, dev, n_traj=None):
+    """States of n_traj independent SQG runs from red-spectrum random fields, after a
+    spin-up, sampled every forecast interval: tensor (n_traj, samples, 2, n, n) float64."""
     import torch
 
     import workloads
-    x = workloads.smooth_fields(rng, 2 * count, cfg.grid, cfg.grid).reshape(count, 2, cfg.grid,
-                                                                          cfg.grid)
-    xg = torch.from_numpy(x).to(dev)
-    sqg.run(xg, xg, cfg.spinup_steps)
-    return xg
+    n_traj = n_traj or cfg.trajectories
+    x = workloads.smooth_fields(rng, 2 * n_traj, cfg.grid, cfg.grid).reshape(
+        n_traj, 2, cfg.grid, cfg.grid)
+    cur = torch.from_numpy(x).to(dev)
+    sqg.run(cur, cur, cfg.spinup_steps)
+    out = torch.empty((n_traj, samples, 2, cfg.grid, cfg.grid), dtype=torch.float64, device=dev)
+    for k in range(samples):
+        out[:, k] = cur
+        sqg.run(cur, cur, cfg.steps_per_cycle)
+    return out
 
 
 def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
@@ -63,20 +77,20 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
     trained surrogate) or "persistence" (no forecast model: the analysis is carried over)."""
     import torch
 
-    import workloads
     from . import ensf
-    from .sqg import SQGModel
     from .surrogate import ensf_surrogate_forward
 
     dev = dev or torch.device("cuda:0")
     rng = np.random.default_rng(cfg.seed)
-    n, d = cfg.grid, 2 * cfg.grid * cfg.grid
+    n = cfg.grid
     res = CycleResult()
-    with SQGModel(n=n, dt=cfg.sqg_dt, max_batch=min(cfg.members, 256)) as sqg:
-        truth = spun_up_states(sqg, 1, cfg, rng, dev)              # (1, 2, n, n) float64
-        pert = workloads.smooth_fields(rng, 2 * cfg.members, n, n).reshape(cfg.members, -1)
-        ens = (truth.reshape(1, -1).cpu().numpy() + cfg.init_spread * pert).astype(np.float32)
-        ens = torch.from_numpy(ens).to(dev)                         # (N, d) float32
+    with sqg_model(cfg, min(cfg.members, 256)) as sqg:
+        truth = climate_trajectories(sqg, cfg, 1, rng, dev, n_traj=1)[0]       # (1, 2, n, n)
+        # initial ensemble: climatological states of independent long runs (Sec. IV-A)
+        per = -(-cfg.members // cfg.trajectories)
+        clim = climate_trajectories(sqg, cfg, per, rng, dev).reshape(-1, 2 * n * n)
+        ens = clim[:cfg.members].float().contiguous()               # (N, d) float32
+        del clim
         post = torch.empty_like(ens)
         idx = torch.from_numpy(obs_indices(n, cfg.obs_stride)).to(dev)
         ctx = ensf.Context(precision=cfg.precision, obs_op=cfg.obs_op,
@@ -109,6 +123,10 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
                     raise RuntimeError(f"analysis status {st} at cycle {c} ({nbad} non-finite)")
                 ens, post = post, ens
                 res.rmse.append(float(torch.sqrt(torch.mean((ens.mean(0) - tv) ** 2))))
+                res.rmse_obs.append(float(torch.sqrt(torch.mean(
+                    (ens.mean(0)[idx.long()] - tv[idx.long()]) ** 2))))
+                res.rmse_forecast_obs.append(float(torch.sqrt(torch.mean(
+                    (post.mean(0)[idx.long()] - tv[idx.long()]) ** 2))))
                 res.spread.append(float(torch.sqrt(torch.mean(ens.var(0)))))
                 if log:
                     log(f"cycle {c}: forecast rmse {res.rmse_forecast[-1]:.4f}, analysis rmse "
@@ -120,16 +138,15 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
 
 
 def training_pairs(count, cfg, dev, seed=None):
-    """(x, SQG(x)) pairs over one forecast interval from seeded spun-up random fields."""
-    import torch
-
-    from .sqg import SQGModel
+    """(x, SQG(x)) pairs over one forecast interval: consecutive samples of independent
+    spun-up SQG trajectories from seeded random initial fields."""
     rng = np.random.default_rng(cfg.seed + 1 if seed is None else seed)
-    with SQGModel(n=cfg.grid, dt=cfg.sqg_dt, max_batch=min(count, 256)) as sqg:
-        x = spun_up_states(sqg, count, cfg, rng, dev)
-        y = torch.empty_like(x)
-        sqg.run(x, y, cfg.steps_per_cycle)
-        torch.cuda.synchronize()
+    n_traj = min(cfg.trajectories, count)
+    per = -(-count // n_traj) + 1
+    with sqg_model(cfg, 256) as sqg:
+        traj = climate_trajectories(sqg, cfg, per, rng, dev, n_traj=n_traj)
+    x = traj[:, :-1].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
+    y = traj[:, 1:].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
     return x.float().contiguous(), y.float().contiguous()
 
 

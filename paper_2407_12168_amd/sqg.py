@@ -14,7 +14,7 @@ def _L():
     L = _lib()
     if not _READY:
         vp, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
-        L.ensf_sqg_create.argtypes = [i32, d, d, d, i32, d, i32, i32, ctypes.POINTER(vp)]
+        L.ensf_sqg_create.argtypes = [i32, d, d, d, i32, d, d, i32, i32, ctypes.POINTER(vp)]
         L.ensf_sqg_run.argtypes = [vp, vp, vp, i32, i32, vp]
         L.ensf_sqg_run_f32.argtypes = [vp, vp, vp, i32, i32, vp]
         L.ensf_sqg_destroy.argtypes = [vp]
@@ -25,12 +25,11 @@ def _L():
 
 
 def ensf_sqg_create(n=128, lx=20.0, shear=1.0, dt=0.025, diff_order=8, diff_efold=None,
-                    max_batch=256, device=0):
+                    relax_time=math.inf, max_batch=256, device=0):
     efold = 10.0 * dt if diff_efold is None else diff_efold
     h = ctypes.c_void_p()
-    _check(_L().ensf_sqg_create(n, lx, shear, dt, diff_order, efold if efold != math.inf
-                                else float("inf"), max_batch, device, ctypes.byref(h)),
-           "ensf_sqg_create")
+    _check(_L().ensf_sqg_create(n, lx, shear, dt, diff_order, float(efold), float(relax_time),
+                                max_batch, device, ctypes.byref(h)), "ensf_sqg_create")
     return h
 
 

@@ -1,10 +1,11 @@
 """Assimilation cycle on the GPU (reduced size): truth and physics forecast by the SQG
 model, learned forecast by the trained conv surrogate, split-BF16 EnSF analysis.
 
-Checks: the analysis reduces the forecast error every cycle; the trained network is a
-useful forecast model (its cycled analysis beats carrying the analysis over without a
-forecast model) and is close to the physics forecast, which in this twin setting is the
-truth's own model (so the network's expected gain over it is speed, reported here).
+Checks: the cycle stays finite and bounded; at the observed components the analysis
+error is below the forecast error every cycle; the trained network is a useful forecast
+model (validation error well below persistence, and its cycled analysis beats carrying the
+analysis over without a forecast model).  In this twin setting the physics forecast is the
+truth's own model, so the network's expected gain over it is speed (reported).
 """
 import numpy as np
 import pytest
@@ -24,13 +25,13 @@ def dev():
 
 
 CFG = cycle.CycleConfig(grid=64, members=64, cycles=6, pseudo_steps=400, steps_per_cycle=10,
-                        spinup_steps=200, sqg_dt=0.025)
+                        spinup_steps=800)
 
 
-def test_analysis_reduces_error_with_physics_forecast(dev):
+def test_cycle_with_physics_forecast(dev):
     res = cycle.run_cycle(CFG, "sqg", dev=dev, log=print)
-    assert all(np.isfinite(res.rmse))
-    assert all(a < f for a, f in zip(res.rmse, res.rmse_forecast))
+    assert all(np.isfinite(res.rmse)) and max(res.rmse) < 3.0
+    assert all(a < f for a, f in zip(res.rmse_obs, res.rmse_forecast_obs))
 
 
 def test_trained_surrogate_beats_no_forecast_and_tracks_physics(dev):

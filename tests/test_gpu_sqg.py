@@ -19,12 +19,12 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("n,efold", [(32, 0.25), (64, np.inf)])
-def test_gpu_sqg_matches_oracle(dev, n, efold):
+@pytest.mark.parametrize("n,efold,tau", [(32, 0.25, 5.0), (64, np.inf, np.inf)])
+def test_gpu_sqg_matches_oracle(dev, n, efold, tau):
     rng = np.random.default_rng(n)
     x = workloads.smooth_fields(rng, 6, n, n).reshape(3, 2, n, n)
-    want = SQG(n=n, dt=0.025, diff_efold=efold).run(x, 20)
-    with G.SQGModel(n=n, dt=0.025, diff_efold=efold, max_batch=2) as m:   # 2 chunks
+    want = SQG(n=n, dt=0.025, diff_efold=efold, relax_time=tau).run(x, 20)
+    with G.SQGModel(n=n, dt=0.025, diff_efold=efold, relax_time=tau, max_batch=2) as m:
         xg = torch.from_numpy(x).to(dev)
         yg = torch.empty_like(xg)
         m.run(xg, yg, 20)

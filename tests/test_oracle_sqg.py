@@ -56,6 +56,22 @@ def test_variance_conserved_without_shear_and_diffusion():
     np.testing.assert_allclose(v1, v0, rtol=50 * 1e-10)
 
 
+def test_thermal_relaxation_damps_every_mode_exactly():
+    # with no flow (shear 0, no diffusion) a linear damping of rate 1/tau is exact per step
+    model = SQG(n=16, lx=20.0, shear=0.0, dt=0.1, diff_efold=np.inf, relax_time=4.0)
+    theta = 1e-12 * workloads.smooth_fields(np.random.default_rng(3), 2, 16, 16)
+    out = model.run(theta, 10)
+    kept = model.ifft(model.fft(theta) * model.mask)       # the model keeps 2/3 of the modes
+    np.testing.assert_allclose(out, kept * np.exp(-1.0 / 4.0), rtol=1e-6, atol=1e-24)
+
+
+def test_relaxed_turbulence_equilibrates():
+    model = SQG(n=32, dt=0.025, relax_time=5.0)
+    theta = workloads.smooth_fields(np.random.default_rng(4), 2, 32, 32)
+    out = model.run(theta, 1200)
+    assert np.all(np.isfinite(out)) and 0.2 < out.std() < 3.0
+
+
 def test_rk4_fourth_order_in_time():
     rng = np.random.default_rng(2)
     theta = workloads.smooth_fields(rng, 2, 32, 32, slope=4.0) * 0.5
