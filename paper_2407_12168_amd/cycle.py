@@ -23,10 +23,10 @@ class CycleConfig:
     pseudo_steps: int = 400      # EM-stable for sigma_o = 0.05
     precision: str = "bf16x3"
     spread_relax: float = 1.0    # relax the analysis spread to the prior spread
-    sqg_dt: float = 0.025
+    sqg_dt: float = 0.0125       # CFL-safe at 128^2 through the spin-up transient
     relax_time: float = 5.0      # SQG thermal relaxation (lets the turbulence equilibrate)
-    steps_per_cycle: int = 20    # forecast length between analyses (0.5 time units)
-    spinup_steps: int = 800
+    steps_per_cycle: int = 40    # forecast length between analyses (0.5 time units)
+    spinup_steps: int = 1600     # 20 time units
     trajectories: int = 16       # independent SQG runs the climatological states come from
     seed: int = 2412
     filter_seed: int = 12173
@@ -140,11 +140,14 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
 def training_pairs(count, cfg, dev, seed=None):
     """(x, SQG(x)) pairs over one forecast interval: consecutive samples of independent
     spun-up SQG trajectories from seeded random initial fields."""
+    import torch
     rng = np.random.default_rng(cfg.seed + 1 if seed is None else seed)
     n_traj = min(cfg.trajectories, count)
     per = -(-count // n_traj) + 1
     with sqg_model(cfg, 256) as sqg:
         traj = climate_trajectories(sqg, cfg, per, rng, dev, n_traj=n_traj)
+    if not bool(torch.isfinite(traj).all()):
+        raise RuntimeError("SQG trajectory became non-finite (reduce sqg_dt)")
     x = traj[:, :-1].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
     y = traj[:, 1:].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
     return x.float().contiguous(), y.float().contiguous()

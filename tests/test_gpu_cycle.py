@@ -24,8 +24,8 @@ def dev():
     return torch.device("cuda:0")
 
 
-CFG = cycle.CycleConfig(grid=64, members=64, cycles=6, pseudo_steps=400, steps_per_cycle=10,
-                        spinup_steps=800)
+CFG = cycle.CycleConfig(grid=64, members=64, cycles=6, pseudo_steps=400, sqg_dt=0.025,
+                        steps_per_cycle=10, spinup_steps=800)
 
 
 def test_cycle_with_physics_forecast(dev):
