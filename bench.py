@@ -190,7 +190,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=30, help="config 5: surrogate epochs")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16x3", "bf16"))
     ap.add_argument("--other-form", default=None,
-                    help="second precision reported alongside (default: the other of fp32/bf16x3)")
+                    help="second precision reported alongside (default: the other of "
+                         "fp32/bf16x3; 'none' to skip)")
     ap.add_argument("--cpu-particles", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
@@ -215,8 +216,9 @@ def main():
     ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev)
     print(f"# {a.precision}: {ms:.3f} ms per analysis", file=sys.stderr, flush=True)
     other = a.other_form or ("bf16x3" if a.precision == "fp32" else "fp32")
-    ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev)
-    print(f"# {other}: {ms2:.3f} ms per analysis", file=sys.stderr, flush=True)
+    if other != "none":
+        ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev)
+        print(f"# {other}: {ms2:.3f} ms per analysis", file=sys.stderr, flush=True)
     ndk = sum(p.n_members * p.dim * p.n_steps for p in probs)
     p0 = probs[0]
     cfg = {"workload": WORKLOAD[a.config], "precision": a.precision}
@@ -236,10 +238,12 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "roofline": roofline(probs, a.precision, phase),
-        "forms": {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
-                          "roofline": roofline(probs, other, phase2)},
-                  "speedup_bf16x3_over_fp32": (ms / ms2) if a.precision == "fp32" else (ms2 / ms)},
     }
+    if other != "none":
+        line["forms"] = {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
+                                 "roofline": roofline(probs, other, phase2)},
+                         "speedup_bf16x3_over_fp32":
+                             (ms / ms2) if a.precision == "fp32" else (ms2 / ms)}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(probs, a.cpu_particles)
     print(json.dumps(line), flush=True)
