@@ -34,8 +34,9 @@ WORKLOAD = {
        "2x256x256}, N=M_p uniform in 32..512, arctan obs of 10-100% of components, "
        "sigma_o=0.05, K=100",
     5: "learned-forecast assimilation cycle: 50 cycles on 2x128x128 SQG states, N=M_p=512, "
-       "forecast by a 6-layer 3x3 conv net (64 channels) trained on 2000 SQG pairs, "
-       "split-BF16 EnSF analysis of obs every 4th grid point (sigma_o=0.05, K=400)",
+       "forecast (0.125 time units) by a 6-layer 3x3 conv net (64 channels) trained on 2000 "
+       "SQG pairs, split-BF16 EnSF analysis of identity obs every 4th grid point "
+       "(sigma_o=0.05, K=400)",
 }
 
 

@@ -25,7 +25,9 @@ class CycleConfig:
     spread_relax: float = 1.0    # relax the analysis spread to the prior spread
     sqg_dt: float = 0.0125       # CFL-safe at 128^2 through the spin-up transient
     relax_time: float = 5.0      # SQG thermal relaxation (lets the turbulence equilibrate)
-    steps_per_cycle: int = 40    # forecast length between analyses (0.5 time units)
+    # forecast length between analyses: 0.125 time units, over which features move a few
+    # grid lengths, within the conv surrogate's 13 x 13 receptive field
+    steps_per_cycle: int = 10
     spinup_steps: int = 1600     # 20 time units
     trajectories: int = 16       # independent SQG runs the climatological states come from
     seed: int = 2412
