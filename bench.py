@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# calibrated with a plain copy of known size (profiles/hbm_traffic_d32768_n256_fp32.md);
+# keyed by (workload config, precision, kernel).  Absent entries are reported as null.
+MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 106.4e6}
 WORKLOAD = {
     1: "EnSF analysis d=2x64x64=8192, N=M_p=20, arctan obs of all components, sigma_o=0.05, K=100",
     2: "EnSF analysis d=2x128x128=32768, N=M_p=256, arctan obs of a random 25% subset, "
@@ -143,15 +147,16 @@ def run_form(probs, precision, steps, warmup, dev):
     return ms, [m / n_launch for m in phase_ms]
 
 
-def roofline(probs, precision, phase_avg_ms):
+def roofline(probs, precision, phase_avg_ms, config=None):
     # algorithmic flops per launch: Gram = sum 2*M_p*N*d, W.X the same (split forms issue 3x)
     flops = sum(2.0 * p.n_members * p.n_members * p.dim for p in probs)
     names = ("k_gram", "k_softmax", "k_wx")
     dom = 0 if phase_avg_ms[0] >= phase_avg_ms[2] else 2
     achieved = flops / (phase_avg_ms[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
+    traffic = MEASURED_TRAFFIC.get((config, precision, names[dom]))
     return {"kernel": names[dom], "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "avg_launch_ms": round(phase_avg_ms[dom], 5),
             "phase_avg_ms": {n: round(v, 5) for n, v in zip(names, phase_avg_ms)}}
 
@@ -238,11 +243,11 @@ def main():
         "dtype": "f32" if a.precision == "fp32" else a.precision,
         "data": "synthetic",
         "config": cfg,
-        "roofline": roofline(probs, a.precision, phase),
+        "roofline": roofline(probs, a.precision, phase, a.config),
     }
     if other != "none":
         line["forms"] = {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
-                                 "roofline": roofline(probs, other, phase2)},
+                                 "roofline": roofline(probs, other, phase2, a.config)},
                          "speedup_bf16x3_over_fp32":
                              (ms / ms2) if a.precision == "fp32" else (ms2 / ms)}
     if not a.no_cpu:
