@@ -262,46 +262,75 @@ __device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t ke
 constexpr int kPingPongBytes = 96 * 1024;
 
 // Operand loaders.  "Kmaj" sources are row-major with k contiguous (Z, X for the Gram,
-// W for W.X); the FP32 W.X B operand X is row-major with the output column contiguous.
+// W for W.X); the FP32 W.X operand X is row-major with the output column contiguous.
+// init() fixes a thread's base address once; load(k0) issues global (not flat) vector loads
+// at base + k0 (flat loads would share the LDS wait counter with the fragment reads), and
+// consecutive slots of a thread are a constant row stride apart.
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  typedef const __attribute__((address_space(1))) T* gptr_t;
+  return *(gptr_t)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, const T& v) {
+  typedef __attribute__((address_space(1))) T* gptr_t;
+  *(gptr_t)p = v;
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// RNE split of two FP32 values into packed bf16 hi and lo pairs (x - hi is exact in FP32).
+__device__ __forceinline__ void split_pair(f32x2 x, uint32_t& hi, uint32_t& lo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2_t));
+  const f32x2 hf = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xFFFF0000u)};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(x - hf, bf16x2_t));
+}
 
 // FP32 source, k contiguous, ROWS x BK tile -> registers (f32x4 per slot).
 template <int ROWS, int NT, int BK>
 struct F32KmajLoad {
   static constexpr int kSlots = ROWS * BK / 4 / NT;
+  static constexpr int kRowStep = NT / (BK / 4);
   static_assert(kSlots * NT * 4 == ROWS * BK, "tile must split evenly");
   f32x4 v[kSlots];
-  __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t row0, int64_t k0) {
+  const float* base;
+  int64_t step;
+  __device__ __forceinline__ void init(const float* src, int64_t ld, int64_t row0) {
+    base = src + (row0 + threadIdx.x / (BK / 4)) * ld + (threadIdx.x % (BK / 4)) * 4;
+    step = kRowStep * ld;
+  }
+  __device__ __forceinline__ void load(int64_t k0) {
+    const float* p = base + k0;
 #pragma unroll
-    for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
-      v[it] = *reinterpret_cast<const f32x4*>(src + (row0 + r) * ld + k0 + c * 4);
-    }
+    for (int it = 0; it < kSlots; ++it) v[it] = gload(reinterpret_cast<const f32x4*>(p + it * step));
   }
   // FP32 smem, k-major [k][row]
   __device__ __forceinline__ void store_kmajor(float* s, int lds) const {
+    const int r = threadIdx.x / (BK / 4), c = threadIdx.x % (BK / 4);
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
-      s[(c * 4 + 0) * lds + r] = v[it].x;
-      s[(c * 4 + 1) * lds + r] = v[it].y;
-      s[(c * 4 + 2) * lds + r] = v[it].z;
-      s[(c * 4 + 3) * lds + r] = v[it].w;
+      float* d = s + (c * 4) * lds + r + it * kRowStep;
+      d[0] = v[it].x;
+      d[lds] = v[it].y;
+      d[2 * lds] = v[it].z;
+      d[3 * lds] = v[it].w;
     }
   }
   // split to bf16 hi/lo, row-major [row][k]
   template <bool LO>
   __device__ __forceinline__ void store_split(uint16_t* sh, uint16_t* sl, int lds) const {
+    const int r = threadIdx.x / (BK / 4), c = threadIdx.x % (BK / 4);
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (BK / 4), c = idx % (BK / 4);
-      uint16_t h0, h1, h2, h3, l0, l1, l2, l3;
-      split_bf16(v[it].x, h0, l0);
-      split_bf16(v[it].y, h1, l1);
-      split_bf16(v[it].z, h2, l2);
-      split_bf16(v[it].w, h3, l3);
-      *reinterpret_cast<u32x2*>(sh + r * lds + c * 4) = u32x2{pack2(h0, h1), pack2(h2, h3)};
-      if constexpr (LO)
-        *reinterpret_cast<u32x2*>(sl + r * lds + c * 4) = u32x2{pack2(l0, l1), pack2(l2, l3)};
+      uint32_t h01, l01, h23, l23;
+      split_pair(f32x2{v[it].x, v[it].y}, h01, l01);
+      split_pair(f32x2{v[it].z, v[it].w}, h23, l23);
+      const int o = (r + it * kRowStep) * lds + c * 4;
+      *reinterpret_cast<u32x2*>(sh + o) = u32x2{h01, h23};
+      if constexpr (LO) *reinterpret_cast<u32x2*>(sl + o) = u32x2{l01, l23};
     }
   }
 };
@@ -310,21 +339,26 @@ struct F32KmajLoad {
 template <int COLS, int NT, int BK>
 struct F32NmajLoad {
   static constexpr int kSlots = COLS * BK / 4 / NT;
+  static constexpr int kRowStep = NT / (COLS / 4);
   static_assert(kSlots * NT * 4 == COLS * BK, "tile must split evenly");
   f32x4 v[kSlots];
-  __device__ __forceinline__ void load(const float* src, int64_t ld, int64_t k0, int64_t col0) {
+  const float* base;
+  int64_t ld;
+  __device__ __forceinline__ void init(const float* src, int64_t ld_, int64_t col0) {
+    ld = ld_;
+    base = src + (int64_t)(threadIdx.x / (COLS / 4)) * ld + col0 + (threadIdx.x % (COLS / 4)) * 4;
+  }
+  __device__ __forceinline__ void load(int64_t k0) {
+    const float* p = base + k0 * ld;
+    const int64_t step = kRowStep * ld;
 #pragma unroll
-    for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (COLS / 4), c = idx % (COLS / 4);
-      v[it] = *reinterpret_cast<const f32x4*>(src + (k0 + r) * ld + col0 + c * 4);
-    }
+    for (int it = 0; it < kSlots; ++it) v[it] = gload(reinterpret_cast<const f32x4*>(p + it * step));
   }
   __device__ __forceinline__ void store(float* s, int lds) const {
+    const int r = threadIdx.x / (COLS / 4), c = threadIdx.x % (COLS / 4);
 #pragma unroll
-    for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT, r = idx / (COLS / 4), c = idx % (COLS / 4);
-      *reinterpret_cast<f32x4*>(s + r * lds + c * 4) = v[it];
-    }
+    for (int it = 0; it < kSlots; ++it)
+      *reinterpret_cast<f32x4*>(s + (r + it * kRowStep) * lds + c * 4) = v[it];
   }
 };
 
@@ -333,28 +367,35 @@ template <int ROWS, int NT, bool LO, int BK>
 struct Bf16KmajLoad {
   static constexpr int kSlots = (ROWS * BK / 8 + NT - 1) / NT;
   static constexpr int kVec = ROWS * BK / 8;
+  static constexpr int kRowStep = NT / (BK / 8);
   u32x4 h[kSlots], l[kSlots];
-  __device__ __forceinline__ void load(const uint16_t* srch, const uint16_t* srcl, int64_t ld,
-                                       int64_t row0, int64_t k0) {
+  const uint16_t* bh;
+  const uint16_t* bl;
+  int64_t step;
+  __device__ __forceinline__ void init(const uint16_t* srch, const uint16_t* srcl, int64_t ld,
+                                       int64_t row0) {
+    const int64_t off = (row0 + threadIdx.x / (BK / 8)) * ld + (threadIdx.x % (BK / 8)) * 8;
+    bh = srch + off;
+    bl = srcl + off;
+    step = kRowStep * ld;
+  }
+  __device__ __forceinline__ void load(int64_t k0) {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (kVec % NT == 0 || idx < kVec) {
-        const int r = idx / (BK / 8), c = idx % (BK / 8);
-        const int64_t off = (row0 + r) * ld + k0 + c * 8;
-        h[it] = *reinterpret_cast<const u32x4*>(srch + off);
-        if constexpr (LO) l[it] = *reinterpret_cast<const u32x4*>(srcl + off);
+      if (kVec % NT == 0 || (int)threadIdx.x + it * NT < kVec) {
+        h[it] = gload(reinterpret_cast<const u32x4*>(bh + k0 + it * step));
+        if constexpr (LO) l[it] = gload(reinterpret_cast<const u32x4*>(bl + k0 + it * step));
       }
     }
   }
   __device__ __forceinline__ void store(uint16_t* sh, uint16_t* sl, int lds) const {
+    const int r = threadIdx.x / (BK / 8), c = threadIdx.x % (BK / 8);
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (kVec % NT == 0 || idx < kVec) {
-        const int r = idx / (BK / 8), c = idx % (BK / 8);
-        *reinterpret_cast<u32x4*>(sh + r * lds + c * 8) = h[it];
-        if constexpr (LO) *reinterpret_cast<u32x4*>(sl + r * lds + c * 8) = l[it];
+      if (kVec % NT == 0 || (int)threadIdx.x + it * NT < kVec) {
+        const int o = (r + it * kRowStep) * lds + c * 8;
+        *reinterpret_cast<u32x4*>(sh + o) = h[it];
+        if constexpr (LO) *reinterpret_cast<u32x4*>(sl + o) = l[it];
       }
     }
   }
@@ -394,11 +435,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
   if constexpr (PREC == kFP32) {
     F32KmajLoad<BM, NT, BK> la;
     F32KmajLoad<BN, NT, BK> lb;
+    la.init(P.Z, P.ldz, m0);
+    lb.init(P.Xf, P.ldz, n0);
     tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
         smem, kbeg, kend,
         [&](int64_t kb) {
-          la.load(P.Z, P.ldz, m0, kb);
-          lb.load(P.Xf, P.ldz, n0, kb);
+          la.load(kb);
+          lb.load(kb);
         },
         [&](char* st) {
           float* sA = reinterpret_cast<float*>(st);
@@ -410,11 +453,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
     constexpr bool LO = PREC == kBF16X3;
     F32KmajLoad<BM, NT, BK> la;
     Bf16KmajLoad<BN, NT, LO, BK> lb;
+    la.init(P.Z, P.ldz, m0);
+    lb.init(P.Xh, P.Xl, P.ldz, n0);
     tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
         smem, kbeg, kend,
         [&](int64_t kb) {
-          la.load(P.Z, P.ldz, m0, kb);
-          lb.load(P.Xh, P.Xl, P.ldz, n0, kb);
+          la.load(kb);
+          lb.load(kb);
         },
         [&](char* st) {
           uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
@@ -428,17 +473,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  float* out = P.part + (int64_t)s * P.Mp_pad * P.ldn;
+  const int64_t ldn = P.ldn;
+  float* out = P.part + (int64_t)s * P.Mp_pad * ldn +
+               (m0 + wm * TM * 32 + (lane >> 5) * 4) * ldn + n0 + wn * TN * 32 + (lane & 31);
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t i = m0 + wm * TM * 32 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int64_t j = n0 + wn * TN * 32 + b * 32 + (lane & 31);
-        out[i * P.ldn + j] = acc[a][b][r];
-      }
+      for (int r = 0; r < 16; ++r)
+        gstore(out + (a * 32 + (r >> 2) * 8 + (r & 3)) * ldn + b * 32, acc[a][b][r]);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -583,11 +627,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
   if constexpr (PREC == kFP32) {
     F32NmajLoad<BE, NT, BK> la;   // X rows (members) x components, components contiguous
     F32KmajLoad<BP, NT, BK> lb;   // W particles x members, members contiguous
+    la.init(P.Xf, P.ldz, e0);
+    lb.init(P.W, P.ldn, i0);
     tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
         smem, 0, P.ldn,
         [&](int64_t kb) {
-          la.load(P.Xf, P.ldz, kb, e0);
-          lb.load(P.W, P.ldn, i0, kb);
+          la.load(kb);
+          lb.load(kb);
         },
         [&](char* st) {
           float* sA = reinterpret_cast<float*>(st);
@@ -599,11 +645,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
     constexpr bool LO = PREC == kBF16X3;
     Bf16KmajLoad<BE, NT, LO, BK> la;   // X^T components x members
     Bf16KmajLoad<BP, NT, LO, BK> lb;   // W particles x members
+    la.init(P.XTh, P.XTl, P.ldn, e0);
+    lb.init(P.Wh, P.Wl, P.ldn, i0);
     tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
         smem, 0, P.ldn,
         [&](int64_t kb) {
-          la.load(P.XTh, P.XTl, P.ldn, e0, kb);
-          lb.load(P.Wh, P.Wl, P.ldn, i0, kb);
+          la.load(kb);
+          lb.load(kb);
         },
         [&](char* st) {
           uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
@@ -616,43 +664,55 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
   }
 
   const StepScalars sc = step_scalars(step_time(P, step), P.eps, P.K);
+  // descriptor fields in registers for the epilogue
+  float* const Zp = P.Z;
+  const float* const Ap = P.A;
+  const float* const Bp = P.B;
+  float* const So = P.score_out;
+  const int64_t dd = P.d, ldz = P.ldz, Mp = P.Mp;
+  const int obs_op = P.obs_op;
+  const uint32_t filt = P.filter, k0 = P.seed_lo, k1 = P.seed_hi;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   unsigned int bad = 0;
 #pragma unroll
   for (int b = 0; b < TN; ++b) {
     const int64_t i = i0 + wn * TN * 32 + b * 32 + (lane & 31);
-    if (i >= P.Mp) continue;
+    if (i >= Mp) continue;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
 #pragma unroll
       for (int gq = 0; gq < 4; ++gq) {
         const int64_t e = e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
-        if (e >= P.d) continue;
+        if (e >= dd) continue;
         const float xh0 = acc[a][b][gq * 4 + 0], xh1 = acc[a][b][gq * 4 + 1];
         const float xh2 = acc[a][b][gq * 4 + 2], xh3 = acc[a][b][gq * 4 + 3];
-        float* zp = P.Z + i * P.ldz + e;
-        const f32x4 z = *reinterpret_cast<const f32x4*>(zp);
-        const f32x4 av = *reinterpret_cast<const f32x4*>(P.A + e);
-        const f32x4 bv = *reinterpret_cast<const f32x4*>(P.B + e);
-        const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, P.obs_op);
-        const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, P.obs_op);
-        const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, P.obs_op);
-        const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, P.obs_op);
-        const int64_t rem = P.d - e;
+        f32x4* zp = reinterpret_cast<f32x4*>(Zp + i * ldz + e);
+        const f32x4 z = gload(zp);
+        const f32x4 av = gload(reinterpret_cast<const f32x4*>(Ap + e));
+        const f32x4 bv = gload(reinterpret_cast<const f32x4*>(Bp + e));
+        const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, obs_op);
+        const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, obs_op);
+        const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, obs_op);
+        const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, obs_op);
+        const int64_t rem = dd - e;
         if constexpr (SCORE) {
-          float* so = P.score_out + i * P.d + e;
+          float* so = So + i * dd + e;
           so[0] = s0;
           if (rem > 1) so[1] = s1;
           if (rem > 2) so[2] = s2;
           if (rem > 3) so[3] = s3;
         } else {
-          const f32x4 xi = normals4((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, P);
+          const Words4 w = philox4x32_10((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, filt,
+                                         k0, k1);
+          float n0, n1, n2, n3;
+          box_muller(w.w0, w.w1, n0, n1);
+          box_muller(w.w2, w.w3, n2, n3);
           f32x4 zn;
-          zn.x = em_step(z.x, s0, xi.x, sc);
-          zn.y = em_step(z.y, s1, xi.y, sc);
-          zn.z = em_step(z.z, s2, xi.z, sc);
-          zn.w = em_step(z.w, s3, xi.w, sc);
+          zn.x = em_step(z.x, s0, n0, sc);
+          zn.y = em_step(z.y, s1, n1, sc);
+          zn.z = em_step(z.z, s2, n2, sc);
+          zn.w = em_step(z.w, s3, n3, sc);
           if (rem < 4) {  // ragged tail: keep the padding at zero
             zn.w = 0.0f;
             if (rem < 3) zn.z = 0.0f;
@@ -660,7 +720,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
           }
           if (!isfinite(zn.x + zn.y + zn.z + zn.w))
             bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
-          *reinterpret_cast<f32x4*>(zp) = zn;
+          gstore(zp, zn);
         }
       }
     }

@@ -30,6 +30,14 @@ class CycleConfig:
     steps_per_cycle: int = 10
     spinup_steps: int = 1600     # 20 time units
     trajectories: int = 16       # independent SQG runs the climatological states come from
+    # surrogate training set: this fraction of the pairs starts from a climatological state
+    # plus a random perturbation (a red-spectrum field and white noise, amplitudes drawn
+    # uniformly up to these multiples of the climatological standard deviation), with the
+    # SQG evolution of the perturbed state as the target, so that the surrogate also sees
+    # states off the attractor such as analysis ensembles
+    train_perturbed: float = 0.5
+    perturb_smooth: float = 1.0
+    perturb_white: float = 0.3
     seed: int = 2412
     filter_seed: int = 12173
 
@@ -139,19 +147,39 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
     return res
 
 
-def training_pairs(count, cfg, dev, seed=None):
+def training_pairs(count, cfg, dev, seed=None, perturbed=None):
     """(x, SQG(x)) pairs over one forecast interval: consecutive samples of independent
-    spun-up SQG trajectories from seeded random initial fields."""
+    spun-up SQG trajectories from seeded random initial fields; a fraction `perturbed`
+    (default cfg.train_perturbed) of the inputs is perturbed first and evolved again."""
     import torch
+
+    import workloads
     rng = np.random.default_rng(cfg.seed + 1 if seed is None else seed)
     n_traj = min(cfg.trajectories, count)
     per = -(-count // n_traj) + 1
+    frac = cfg.train_perturbed if perturbed is None else perturbed
     with sqg_model(cfg, 256) as sqg:
         traj = climate_trajectories(sqg, cfg, per, rng, dev, n_traj=n_traj)
-    if not bool(torch.isfinite(traj).all()):
+        x = traj[:, :-1].reshape(-1, 2, cfg.grid, cfg.grid)[:count].clone()
+        y = traj[:, 1:].reshape(-1, 2, cfg.grid, cfg.grid)[:count].clone()
+        del traj
+        n_pert = int(round(frac * count))
+        if n_pert > 0:
+            sel = torch.from_numpy(rng.choice(count, n_pert, replace=False)).to(dev)
+            clim_std = float(x.std())
+            a_s = rng.uniform(0.0, cfg.perturb_smooth, n_pert) * clim_std
+            a_w = rng.uniform(0.0, cfg.perturb_white, n_pert) * clim_std
+            red = workloads.smooth_fields(rng, 2 * n_pert, cfg.grid, cfg.grid).reshape(
+                n_pert, 2, cfg.grid, cfg.grid)
+            white = rng.standard_normal((n_pert, 2, cfg.grid, cfg.grid))
+            pert = a_s[:, None, None, None] * red + a_w[:, None, None, None] * white
+            xp = x[sel] + torch.from_numpy(pert).to(dev)
+            yp = torch.empty_like(xp)
+            sqg.run(xp, yp, cfg.steps_per_cycle)
+            x[sel] = xp
+            y[sel] = yp
+    if not (bool(torch.isfinite(x).all()) and bool(torch.isfinite(y).all())):
         raise RuntimeError("SQG trajectory became non-finite (reduce sqg_dt)")
-    x = traj[:, :-1].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
-    y = traj[:, 1:].reshape(-1, 2, cfg.grid, cfg.grid)[:count]
     return x.float().contiguous(), y.float().contiguous()
 
 
