@@ -36,8 +36,8 @@ class CycleConfig:
     # SQG evolution of the perturbed state as the target, so that the surrogate also sees
     # states off the attractor such as analysis ensembles
     train_perturbed: float = 0.5
-    perturb_smooth: float = 1.0
-    perturb_white: float = 0.3
+    perturb_smooth: float = 0.5
+    perturb_white: float = 0.1
     seed: int = 2412
     filter_seed: int = 12173
 
