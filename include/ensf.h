@@ -143,9 +143,13 @@ ensf_status ensf_ensemble_stats(const float* d_ens, int32_t n, int64_t dim,
    indices, ENSF_ENONFINITE (with *nonfinite_count set) for NaN/Inf particles. */
 ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count);
 
-/* Times the candidate tile shapes on the given problem (running it several times on
+/* Times candidate kernel variants on the given problem (running it several times on
    the stream; d_post is overwritten) and records the fastest in the context's table
-   and, if set, the tune_cache file. */
+   and, if set, the tune_cache file.  The search is coordinate-wise: Gram tile, split-K
+   scale, k-step depth and LDS stage count with the W.X variant fixed, then the W.X tile,
+   k-step depth and stage count, then the Gram side again.  Cache entries map a key
+   "gfx950/p<precision>/n<log2 N>/m<log2 M_p>/d<log2 d>" to
+   [gram tile, W.X tile, split scale, Gram k-step, W.X k-step, Gram stages, W.X stages]. */
 ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream);
 
 /* Phase timing: with enable = 1 the context runs the pseudo-time loop eagerly and records

@@ -43,7 +43,14 @@ struct TileChoice {
   int gram = kGram128;
   int wx = kWx128;
   double split_scale = 1.0;  // multiplies the default split-K count
-  int bk = 32;               // k-step depth of the MFMA main loops (32 or 64)
+  int gram_bk = 32;          // k-step depth of the Gram main loop (32 or 64)
+  int wx_bk = 32;            // k-step depth of the W.X main loop (32 or 64)
+  int gram_st = 2;           // LDS stages of the Gram main loop (1, or 2 = ping-pong)
+  int wx_st = 2;             // LDS stages of the W.X main loop
+  bool same_kernels(const TileChoice& o) const {
+    return gram == o.gram && wx == o.wx && gram_bk == o.gram_bk && wx_bk == o.wx_bk &&
+           gram_st == o.gram_st && wx_st == o.wx_st;
+  }
 };
 
 struct GraphKey {
@@ -283,7 +290,7 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
     int g = 0;
     for (; g < (int)plan.groups.size(); ++g) {
       const TileChoice& t = plan.groups[g].tiles;
-      if (t.gram == tc[f].gram && t.wx == tc[f].wx && t.bk == tc[f].bk) break;
+      if (t.same_kernels(tc[f])) break;
     }
     if (g == (int)plan.groups.size()) {
       plan.groups.emplace_back();
@@ -434,15 +441,15 @@ ensf_status ensure_softmax_smem(ensf_ctx* c, int max_ldn) {
 
 ensf_status launch_grams(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k, hipStream_t s) {
   for (size_t g = 0; g < plan.groups.size(); ++g)
-    HIP_TRY(launch_gram(c->opt.precision, plan.groups[g].tiles.gram, plan.groups[g].tiles.bk,
-                        u.gram[g], k, s));
+    HIP_TRY(launch_gram(c->opt.precision, plan.groups[g].tiles.gram, plan.groups[g].tiles.gram_bk,
+                        plan.groups[g].tiles.gram_st, u.gram[g], k, s));
   return ENSF_OK;
 }
 
 ensf_status launch_wxs(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k, hipStream_t s) {
   for (size_t g = 0; g < plan.groups.size(); ++g)
-    HIP_TRY(launch_wx(c->opt.precision, plan.groups[g].tiles.wx, plan.groups[g].tiles.bk, false,
-                      u.wx[g], k, c->d_counters, s));
+    HIP_TRY(launch_wx(c->opt.precision, plan.groups[g].tiles.wx, plan.groups[g].tiles.wx_bk,
+                      plan.groups[g].tiles.wx_st, false, u.wx[g], k, c->d_counters, s));
   return ENSF_OK;
 }
 
@@ -518,7 +525,8 @@ ensf_status run_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStrea
   addp(c->d_counters);
   for (size_t g = 0; g < plan.groups.size(); ++g) {
     const TileChoice& t = plan.groups[g].tiles;
-    key.sig.insert(key.sig.end(), {t.gram, t.wx, t.bk, u.gram[g].np, u.gram[g].total, u.wx[g].total});
+    key.sig.insert(key.sig.end(), {t.gram, t.wx, t.gram_bk, t.wx_bk, t.gram_st, t.wx_st,
+                                   u.gram[g].np, u.gram[g].total, u.wx[g].total});
     addp(u.gram[g].desc);
     addp(u.gram[g].pre);
     addp(u.wx[g].pre);
@@ -599,11 +607,19 @@ void load_tune_cache(ensf_ctx* c) {
     const size_t end = txt.find('"', pos + 1);
     if (end == std::string::npos) break;
     const std::string key = txt.substr(pos + 1, end - pos - 1);
+    // [gram, wx, split_scale, gram_bk, wx_bk, gram_st, wx_st]; a 4-entry form gives one
+    // k-step depth for both kernels and two stages
     TileChoice tc;
-    const int got = sscanf(txt.c_str() + end + 1, " : [ %d , %d , %lf , %d ]", &tc.gram, &tc.wx,
-                           &tc.split_scale, &tc.bk);
+    int bk = 32;
+    const int got = sscanf(txt.c_str() + end + 1, " : [ %d , %d , %lf , %d , %d , %d , %d ]",
+                           &tc.gram, &tc.wx, &tc.split_scale, &bk, &tc.wx_bk, &tc.gram_st,
+                           &tc.wx_st);
+    tc.gram_bk = bk;
+    if (got == 4) tc.wx_bk = bk;
+    auto ok_bk = [](int v) { return v == 32 || v == 64; };
+    auto ok_st = [](int v) { return v == 1 || v == 2; };
     if (got >= 3 && tc.gram >= 0 && tc.gram < kNumGram && tc.wx >= 0 && tc.wx < kNumWx &&
-        (tc.bk == 32 || tc.bk == 64))
+        ok_bk(tc.gram_bk) && ok_bk(tc.wx_bk) && ok_st(tc.gram_st) && ok_st(tc.wx_st))
       c->tune[key] = tc;
     pos = end + 1;
   }
@@ -616,8 +632,9 @@ void save_tune_cache(ensf_ctx* c) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (const auto& kv : c->tune)
-    fprintf(fp, "  \"%s\": [%d, %d, %.3f, %d]%s\n", kv.first.c_str(), kv.second.gram,
-            kv.second.wx, kv.second.split_scale, kv.second.bk, ++i < c->tune.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %.3f, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.gram,
+            kv.second.wx, kv.second.split_scale, kv.second.gram_bk, kv.second.wx_bk,
+            kv.second.gram_st, kv.second.wx_st, ++i < c->tune.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
 }
@@ -721,9 +738,9 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   if (st != ENSF_OK) return st;
   const int prec = ctx->opt.precision;
   const TileChoice& tiles = plan.groups[0].tiles;
-  HIP_TRY(launch_gram(prec, tiles.gram, tiles.bk, u.gram[0], -1, s));
+  HIP_TRY(launch_gram(prec, tiles.gram, tiles.gram_bk, tiles.gram_st, u.gram[0], -1, s));
   HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
-  HIP_TRY(launch_wx(prec, tiles.wx, 32, true, u.wx[0], -1, ctx->d_counters, s));
+  HIP_TRY(launch_wx(prec, tiles.wx, 32, 2, true, u.wx[0], -1, ctx->d_counters, s));
   ctx->last_stream = s;
   ctx->has_last_stream = true;
   return ENSF_OK;
@@ -771,38 +788,65 @@ ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream)
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  TileChoice best;
-  float best_ms = INFINITY;
   const int use_graph = ctx->opt.use_graph;
   ctx->opt.use_graph = 0;
+  // Time of one candidate: two timed analyses after a warm-up.
+  auto time_of = [&](const TileChoice& tc, float& ms_sum) {
+    ms_sum = 0.0f;
+    for (int rep = 0; rep < 3 && st == ENSF_OK; ++rep) {
+      st = analysis_impl(ctx, probs, s, &tc);  // warm-up on rep 0
+      if (st != ENSF_OK || rep == 0) continue;
+      if (hipEventRecord(e0, s) != hipSuccess) st = ENSF_EHIP;
+      if (st == ENSF_OK) st = analysis_impl(ctx, probs, s, &tc);
+      if (st == ENSF_OK && hipEventRecord(e1, s) != hipSuccess) st = ENSF_EHIP;
+      if (st == ENSF_OK && hipEventSynchronize(e1) != hipSuccess) st = ENSF_EHIP;
+      float ms = 0;
+      if (st == ENSF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = ENSF_EHIP;
+      ms_sum += ms;
+    }
+    return st == ENSF_OK;
+  };
+  // Coordinate search: the Gram side (tile, split-K scale, k-step, stages) with the W.X
+  // side fixed, then the W.X side with the Gram side fixed, then the Gram side again.
+  TileChoice best = heuristic_tiles(p.n_members, p.n_particles);
+  float best_ms = INFINITY;
   const double scales[] = {0.5, 1.0, 2.0};
-  for (int bk : {32, 64})
-  for (int gc = 0; gc < kNumGram; ++gc)
-    for (int wc = 0; wc < kNumWx; ++wc)
-      for (double sc : scales) {
-        TileChoice tc;
-        tc.gram = gc;
-        tc.wx = wc;
-        tc.split_scale = sc;
-        tc.bk = bk;
-        float ms_sum = 0.0f;
-        for (int rep = 0; rep < 3 && st == ENSF_OK; ++rep) {
-          st = analysis_impl(ctx, probs, s, &tc);  // warm-up on rep 0
-          if (st != ENSF_OK || rep == 0) continue;
-          if (hipEventRecord(e0, s) != hipSuccess) st = ENSF_EHIP;
-          if (st == ENSF_OK) st = analysis_impl(ctx, probs, s, &tc);
-          if (st == ENSF_OK && hipEventRecord(e1, s) != hipSuccess) st = ENSF_EHIP;
-          if (st == ENSF_OK && hipEventSynchronize(e1) != hipSuccess) st = ENSF_EHIP;
-          float ms = 0;
-          if (st == ENSF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = ENSF_EHIP;
-          ms_sum += ms;
-        }
-        if (st != ENSF_OK) break;
-        if (ms_sum < best_ms) {
-          best_ms = ms_sum;
-          best = tc;
-        }
-      }
+  for (int pass = 0; pass < 3 && st == ENSF_OK; ++pass) {
+    const TileChoice base = best;
+    if (pass != 1) {
+      for (int gc = 0; gc < kNumGram && st == ENSF_OK; ++gc)
+        for (double sc : scales)
+          for (int bk : {32, 64})
+            for (int ns : {1, 2}) {
+              TileChoice tc = base;
+              tc.gram = gc;
+              tc.split_scale = sc;
+              tc.gram_bk = bk;
+              tc.gram_st = ns;
+              float ms;
+              if (!time_of(tc, ms)) break;
+              if (ms < best_ms) {
+                best_ms = ms;
+                best = tc;
+              }
+            }
+    } else {
+      for (int wc = 0; wc < kNumWx && st == ENSF_OK; ++wc)
+        for (int bk : {32, 64})
+          for (int ns : {1, 2}) {
+            TileChoice tc = base;
+            tc.wx = wc;
+            tc.wx_bk = bk;
+            tc.wx_st = ns;
+            float ms;
+            if (!time_of(tc, ms)) break;
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = tc;
+            }
+          }
+    }
+  }
   ctx->opt.use_graph = use_graph;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -75,7 +75,7 @@ inline int wx_bp(int c) {
   return c == kWx128x256 ? 256 : c == kWx128 || c == kWx256 ? 128 : c == kWx64 ? 64 : 32;
 }
 // k-step depths of the MFMA main loops are template variants (32 or 64); every padding
-// is a multiple of the largest.
+// is a multiple of the largest.  The LDS stage count (1, or 2 = ping-pong) is a variant too.
 constexpr int kMaxBK = 64;
 
 // Remembers the HIP error behind the calling thread's latest failed call
@@ -84,10 +84,10 @@ void record_hip_error(hipError_t e);
 void clear_stale_hip_error();
 
 // Host-callable launchers (ensf_kernels.hip).
-hipError_t launch_gram(int prec, int cfg, int bk, const GroupedLaunch& g, int step,
+hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g, int step,
                        hipStream_t s);
 hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ldn, hipStream_t s);
-hipError_t launch_wx(int prec, int cfg, int bk, bool score_mode, const GroupedLaunch& g,
+hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
                      int step, unsigned long long* nonfinite, hipStream_t s);
 hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s);
 hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s);

@@ -258,7 +258,9 @@ __device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t ke
   }
 }
 
-// Two LDS stages are used when they fit in this budget (leaves room for 1-2 workgroups).
+// With ST = 2 two LDS stages are used when they fit in this budget (leaves room for 1-2
+// workgroups); ST = 1 keeps one stage, which halves the LDS per workgroup and can raise the
+// number of resident workgroups.  Which is faster depends on the shape (the tuner decides).
 constexpr int kPingPongBytes = 96 * 1024;
 
 // Operand loaders.  "Kmaj" sources are row-major with k contiguous (Z, X for the Gram,
@@ -404,11 +406,11 @@ struct Bf16KmajLoad {
 // ----------------------------------------------------------------------------------------
 // Gram: part[s][i][j] = sum_{k in chunk s} Z[i][k] X[j][k]
 
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
   using S = TileSmem<PREC, BM, BN, BK>;
-  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
@@ -599,12 +601,12 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
 // holds four consecutive components of one particle, i.e. exactly the four normals of one
 // Philox counter, so the epilogue runs from the accumulators without any exchange.
 
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool SCORE>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
   using S = TileSmem<PREC, BE, BP, BK>;
-  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
@@ -872,14 +874,19 @@ namespace {
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 }
 
+#define ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, BKV, STV)                                     \
+  hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN, BKV, STV>), dim3(g.total),                \
+                     dim3(64 * WGM * WGN), 0, s, g, step)
 #define ENSF_GRAM_CASE(PR, C, WGM, WGN, TM, TN)                                              \
   if (prec == PR && cfg == C) {                                                              \
-    if (bk == 64)                                                                            \
-      hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN, 64>), dim3(g.total),                  \
-                         dim3(64 * WGM * WGN), 0, s, g, step);                               \
+    if (bk == 64 && st == 2)                                                                 \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 64, 2);                                         \
+    else if (bk == 64)                                                                       \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 64, 1);                                         \
+    else if (st == 2)                                                                        \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 32, 2);                                         \
     else                                                                                     \
-      hipLaunchKernelGGL((k_gram<PR, WGM, WGN, TM, TN, 32>), dim3(g.total),                  \
-                         dim3(64 * WGM * WGN), 0, s, g, step);                               \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 32, 1);                                         \
     return hipGetLastError();                                                                \
   }
 
@@ -889,7 +896,7 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
   ENSF_GRAM_CASE(PR, kGram32, 1, 1, 1, 1)  \
   ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)
 
-hipError_t launch_gram(int prec, int cfg, int bk, const GroupedLaunch& g, int step,
+hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g, int step,
                        hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
   ENSF_GRAM_ALL(kFP32)
@@ -898,17 +905,21 @@ hipError_t launch_gram(int prec, int cfg, int bk, const GroupedLaunch& g, int st
   return hipErrorInvalidValue;
 }
 
-#define ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, BKV, SC)                                        \
-  hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, BKV, SC>), dim3(g.total),                   \
+#define ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, BKV, STV, SC)                                   \
+  hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, BKV, STV, SC>), dim3(g.total),              \
                      dim3(64 * WGM * WGN), 0, s, g, step, nonfinite)
 #define ENSF_WX_CASE(PR, C, WGM, WGN, TM, TN)                                                \
   if (prec == PR && cfg == C) {                                                              \
     if (score_mode)                                                                          \
-      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, true);                                        \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, 2, true);                                     \
+    else if (bk == 64 && st == 2)                                                            \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 64, 2, false);                                    \
     else if (bk == 64)                                                                       \
-      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 64, false);                                       \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 64, 1, false);                                    \
+    else if (st == 2)                                                                        \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, 2, false);                                    \
     else                                                                                     \
-      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, false);                                       \
+      ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, 1, false);                                    \
     return hipGetLastError();                                                                \
   }
 
@@ -920,7 +931,7 @@ hipError_t launch_gram(int prec, int cfg, int bk, const GroupedLaunch& g, int st
   ENSF_WX_CASE(PR, kWx256, 4, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)
 
-hipError_t launch_wx(int prec, int cfg, int bk, bool score_mode, const GroupedLaunch& g,
+hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
                      int step, unsigned long long* nonfinite, hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
   ENSF_WX_ALL(kFP32)
