@@ -152,6 +152,14 @@ ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count);
    [gram tile, W.X tile, split scale, Gram k-step, W.X k-step, Gram stages, W.X stages]. */
 ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream);
 
+/* The same for a batch (an array of n_problems host descriptors, as for
+   ensf_analysis_batched): candidates are timed on the whole batch and recorded under a key
+   made of the largest problem's buckets and the batch size ("gfx950/p<precision>/b<log2
+   n_problems>/n../m../d.."), which is the only entry a batched call consults; a batch
+   without one uses the built-in heuristic. */
+ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs, int32_t n_problems,
+                                  void* stream);
+
 /* Phase timing: with enable = 1 the context runs the pseudo-time loop eagerly and records
    HIP events on the call's stream around every kernel launch; ensf_phase_times then
    waits for them and returns the summed durations in milliseconds of the Gram, softmax

@@ -58,15 +58,30 @@ struct GraphKey {
   bool operator==(const GraphKey& o) const { return sig == o.sig; }
 };
 
-std::string tune_key(int prec, int64_t n, int64_t mp, int64_t d) {
+// Table key: precision and log2 buckets of N, M_p and d; for a batch of several problems
+// those of the dominant problem (most N M_p d) and the log2 bucket of the batch size.
+std::string tune_key(int prec, int64_t n, int64_t mp, int64_t d, int64_t batch = 1) {
   auto bucket = [](int64_t v) {
     int b = 0;
     while ((int64_t(1) << (b + 1)) <= v) ++b;
     return b;
   };
   char buf[96];
-  snprintf(buf, sizeof buf, "gfx950/p%d/n%d/m%d/d%d", prec, bucket(n), bucket(mp), bucket(d));
+  if (batch > 1)
+    snprintf(buf, sizeof buf, "gfx950/p%d/b%d/n%d/m%d/d%d", prec, bucket(batch), bucket(n),
+             bucket(mp), bucket(d));
+  else
+    snprintf(buf, sizeof buf, "gfx950/p%d/n%d/m%d/d%d", prec, bucket(n), bucket(mp), bucket(d));
   return buf;
+}
+
+size_t dominant_problem(const std::vector<ensf_problem>& probs) {
+  size_t dom = 0;
+  for (size_t f = 1; f < probs.size(); ++f)
+    if ((double)probs[f].n_members * probs[f].n_particles * probs[f].dim >
+        (double)probs[dom].n_members * probs[dom].n_particles * probs[dom].dim)
+      dom = f;
+  return dom;
 }
 
 }  // namespace
@@ -263,8 +278,10 @@ ensf_status ensure_table(ensf_ctx* c, size_t bytes) {
   return ENSF_OK;
 }
 
-TileChoice tiles_for(ensf_ctx* c, int prec, const ensf_problem& p) {
-  auto it = c->tune.find(tune_key(prec, p.n_members, p.n_particles, p.dim));
+// A batch uses only a table entry measured on a batch (the fastest variant for its largest
+// problem alone is not the fastest for the batch), else the heuristic.
+TileChoice tiles_for(ensf_ctx* c, int prec, const ensf_problem& p, int64_t batch) {
+  auto it = c->tune.find(tune_key(prec, p.n_members, p.n_particles, p.dim, batch));
   if (it != c->tune.end()) return it->second;
   return heuristic_tiles(p.n_members, p.n_particles);
 }
@@ -279,12 +296,8 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
   // One kernel variant for the whole batch (that of the problem with the most work): a
   // single grouped launch per phase keeps every filter's tiles in flight together, which
   // measured faster than one launch per variant.
-  size_t dominant = 0;
-  for (size_t f = 1; f < probs.size(); ++f)
-    if ((double)probs[f].n_members * probs[f].n_particles * probs[f].dim >
-        (double)probs[dominant].n_members * probs[dominant].n_particles * probs[dominant].dim)
-      dominant = f;
-  const TileChoice batch_tiles = force ? *force : tiles_for(c, prec, probs[dominant]);
+  const size_t dominant = dominant_problem(probs);
+  const TileChoice batch_tiles = force ? *force : tiles_for(c, prec, probs[dominant], np);
   for (int f = 0; f < np; ++f) {
     tc[f] = batch_tiles;
     int g = 0;
@@ -777,14 +790,20 @@ ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count) {
 }
 
 ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream) {
-  if (!ctx || !prob) return ENSF_EINVAL;
-  ensf_status st = validate(*prob);
+  return ensf_autotune_batched(ctx, prob, 1, stream);
+}
+
+ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, int32_t n_problems,
+                                  void* stream) {
+  if (!ctx || !probs_in || n_problems < 1) return ENSF_EINVAL;
+  ensf_status st = ENSF_OK;
+  for (int32_t f = 0; f < n_problems && st == ENSF_OK; ++f) st = validate(probs_in[f]);
   if (st != ENSF_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(ctx->device));
-  ensf_problem p = *prob;
-  p.n_steps = std::min(p.n_steps, 8);
-  std::vector<ensf_problem> probs{p};
+  std::vector<ensf_problem> probs(probs_in, probs_in + n_problems);
+  for (auto& q : probs) q.n_steps = std::min(q.n_steps, 8);
+  const ensf_problem p = probs[dominant_problem(probs)];
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -851,7 +870,7 @@ ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream)
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != ENSF_OK) return st;
-  ctx->tune[tune_key(ctx->opt.precision, p.n_members, p.n_particles, p.dim)] = best;
+  ctx->tune[tune_key(ctx->opt.precision, p.n_members, p.n_particles, p.dim, n_problems)] = best;
   save_tune_cache(ctx);
   return ENSF_OK;
 }

@@ -47,7 +47,7 @@ class ensf_problem(ctypes.Structure):
 _LIB = None
 EXPORTS = ("ensf_default_options", "ensf_create", "ensf_analysis", "ensf_analysis_batched",
            "ensf_score", "ensf_rng_normal", "ensf_ensemble_stats", "ensf_sync_status",
-           "ensf_autotune", "ensf_profile_phases", "ensf_phase_times", "ensf_destroy",
+           "ensf_autotune", "ensf_autotune_batched", "ensf_profile_phases", "ensf_phase_times", "ensf_destroy",
            "ensf_status_string", "ensf_last_error_string")
 
 
@@ -72,6 +72,7 @@ def _lib():
         L.ensf_ensemble_stats.argtypes = [vp, i32, i64, vp, vp, vp]
         L.ensf_sync_status.argtypes = [vp, ctypes.POINTER(i64)]
         L.ensf_autotune.argtypes = [vp, ctypes.POINTER(ensf_problem), vp]
+        L.ensf_autotune_batched.argtypes = [vp, ctypes.POINTER(ensf_problem), i32, vp]
         L.ensf_profile_phases.argtypes = [vp, i32]
         L.ensf_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.ensf_destroy.argtypes = [vp]
@@ -212,6 +213,12 @@ def ensf_sync_status(ctx):
 
 def ensf_autotune(ctx, problem, stream=None):
     _check(_lib().ensf_autotune(ctx, ctypes.byref(problem), _stream(stream)), "ensf_autotune")
+
+
+def ensf_autotune_batched(ctx, problems, stream=None):
+    arr = (ensf_problem * len(problems))(*problems)
+    _check(_lib().ensf_autotune_batched(ctx, arr, len(problems), _stream(stream)),
+           "ensf_autotune_batched")
 
 
 def ensf_profile_phases(ctx, enable):

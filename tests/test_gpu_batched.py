@@ -92,3 +92,27 @@ def test_batched_config4_shapes_small_sample(dev):
     for p, g in zip(ps, got):
         want = O.analysis(p["X"], p["idx"], p["y"], p["sig"], p["K"], p["seed"], p["fid"])
         assert np.abs(g - want).max() <= 5e-4 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_batched_autotune_then_match_oracle(dev, precision, tmp_path):
+    # the batch tuner records an entry under the batch key; the tuned batch still matches
+    probs = _problems(3000)
+    cache = tmp_path / "tune.json"
+    tens, descs = [], []
+    for p in probs:
+        X = torch.from_numpy(p["X"]).to(dev)
+        post = torch.empty((p["M"], p["X"].shape[1]), device=dev)
+        idx = torch.from_numpy(p["idx"]).to(dev)
+        y = torch.from_numpy(p["y"]).to(dev)
+        tens.append((X, post, idx, y))
+        descs.append(ensf.make_problem(X, post, idx, y, p["sig"], p["K"], p["seed"], p["fid"]))
+    with ensf.Context(precision=precision, tune_cache=str(cache)) as ctx:
+        ensf.ensf_autotune_batched(ctx.handle, descs)
+        torch.cuda.synchronize()
+        assert "/b2/" in cache.read_text()   # 5 problems -> batch bucket 2
+        got = _run_batched(dev, probs, precision, ctx)
+    for p, g in zip(probs, got):
+        want = O.analysis(p["X"], p["idx"], p["y"], p["sig"], p["K"], p["seed"], p["fid"],
+                          n_particles=p["M"])
+        assert np.abs(g - want).max() <= 5e-4 * np.abs(want).max()
