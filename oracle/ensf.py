@@ -57,6 +57,15 @@ def likelihood_score(Z, A, B, obs_op="arctan"):
     return A - B * Z
 
 
+def likelihood_curvature(Z, B, obs_op="arctan"):
+    """Gauss-Newton curvature of -log p(y | z) per component: B * g'(z)^2 with g the
+    observation operator (g' = 1 for the identity, 1 / (1 + z^2) for arctan).  It is the
+    stiffness of the likelihood term that the linearly implicit step treats implicitly."""
+    if obs_op == "arctan":
+        return B / (1.0 + Z * Z) ** 2
+    return B * np.ones_like(Z)
+
+
 def prior_weights(Z, X, t, eps=0.05):
     """Monte-Carlo weights of eq. 16: w_ij = Q(z_i | x_j) / sum_j' Q(z_i | x_j'), with
     Q(z | x) proportional to exp(-|z - alpha x|^2 / (2 beta^2)) (eq. 12).
@@ -120,11 +129,21 @@ def initial_particles(seed, filter_id, particle_ids, d):
 
 def analysis(X, obs_idx, obs_val, sigma_o, n_steps, seed, filter_id=0, obs_op="arctan",
              eps=0.05, n_particles=None, particle_ids=None, spread_relax=0.0, chunk=1024,
-             return_all=False):
+             return_all=False, lik_step="explicit"):
     """Analysis ensemble: run the discretised reverse SDE (eq. 7) from N(0, I) with the
     approximate posterior score (eq. 17).  Particles are independent given X, so any
     subset `particle_ids` of the n_particles particles can be run alone; `chunk` bounds
-    the rows of the Gram matrix held at once."""
+    the rows of the Gram matrix held at once.
+
+    lik_step = "explicit" is the plain Euler-Maruyama step of eq. 7 (the paper's "e.g.,
+    an Euler scheme").  lik_step = "implicit" advances the damped likelihood part of the
+    drift, sigma^2 h s_lik(z), linearly implicitly with its Gauss-Newton curvature kappa:
+        z <- z - (b z - sigma^2 s_prior) dt + sigma^2 h s_lik dt / (1 + sigma^2 h kappa dt)
+               + sqrt(sigma^2 dt) xi,
+    which equals the explicit step where there are no observations and stays stable when
+    dt is not small against sigma_o^2 (the explicit step needs dt of order sigma_o^2)."""
+    if lik_step not in ("explicit", "implicit"):
+        raise ValueError(lik_step)
     X = np.asarray(X, dtype=np.float64)
     N, d = X.shape
     if particle_ids is None:
@@ -139,9 +158,17 @@ def analysis(X, obs_idx, obs_val, sigma_o, n_steps, seed, filter_id=0, obs_op="a
         xi = philox.normals(seed, filter_id, k, particle_ids, d)
         for c0 in range(0, Z.shape[0], chunk):
             z = Z[c0:c0 + chunk]
-            S = posterior_score(z, X, A, B, t, eps, obs_op)
-            Z[c0:c0 + chunk] = (z - (sc["b"] * z - sc["sigma2"] * S) * dt
-                                + np.sqrt(sc["sigma2"] * dt) * xi[c0:c0 + chunk])
+            noise = np.sqrt(sc["sigma2"] * dt) * xi[c0:c0 + chunk]
+            if lik_step == "explicit":
+                S = posterior_score(z, X, A, B, t, eps, obs_op)
+                Z[c0:c0 + chunk] = z - (sc["b"] * z - sc["sigma2"] * S) * dt + noise
+            else:
+                Sp = prior_score(z, X, t, eps)
+                L = likelihood_score(z, A, B, obs_op)
+                kap = likelihood_curvature(z, B, obs_op)
+                damp = sc["sigma2"] * sc["h"] * dt
+                Z[c0:c0 + chunk] = (z - (sc["b"] * z - sc["sigma2"] * Sp) * dt
+                                    + damp * L / (1.0 + damp * kap) + noise)
     if spread_relax > 0.0:
         Z = relax_spread(Z, X, spread_relax)
     return Z

@@ -17,17 +17,26 @@ scheme must approach (m, v).  The damped score does not reproduce the Kalman pos
 from .ensf import schedule
 
 
-def em_recursion(mu, s2, A, B, n_steps, eps=0.05):
+def em_recursion(mu, s2, A, B, n_steps, eps=0.05, lik_step="explicit"):
+    """lik_step = "implicit": the likelihood part of the drift, sigma^2 h (A - B z) dt, is
+    divided by (1 + sigma^2 h B dt) (the identity operator's curvature is B), so
+        P = 1 - b dt - sigma^2 dt / v_t - g B,   m <- P m + sigma^2 alpha mu dt / v_t + g A,
+    with g = sigma^2 h dt / (1 + sigma^2 h B dt)."""
     m, v = 0.0, 1.0
     dt = 1.0 / n_steps
     for k in range(n_steps):
         t = 1.0 - k * dt
         sc = schedule(t, eps)
         vt = sc["alpha"] ** 2 * s2 + sc["beta2"]
-        c = 1.0 / vt + sc["h"] * B
-        q = sc["alpha"] * mu / vt + sc["h"] * A
-        P = 1.0 - sc["b"] * dt - sc["sigma2"] * c * dt
-        m = P * m + sc["sigma2"] * q * dt
+        if lik_step == "explicit":
+            c = 1.0 / vt + sc["h"] * B
+            q = sc["alpha"] * mu / vt + sc["h"] * A
+            P = 1.0 - sc["b"] * dt - sc["sigma2"] * c * dt
+            m = P * m + sc["sigma2"] * q * dt
+        else:
+            g = sc["sigma2"] * sc["h"] * dt / (1.0 + sc["sigma2"] * sc["h"] * B * dt)
+            P = 1.0 - sc["b"] * dt - sc["sigma2"] * dt / vt - g * B
+            m = P * m + sc["sigma2"] * sc["alpha"] * mu * dt / vt + g * A
         v = P * P * v + sc["sigma2"] * dt
     return m, v
 
