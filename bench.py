@@ -27,7 +27,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # calibrated with a plain copy of known size (profiles/hbm_traffic_d32768_n256_fp32.md);
 # keyed by (workload config, precision, kernel).  Absent entries are reported as null.
-MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 104.4e6}
+MEASURED_TRAFFIC = {}
 WORKLOAD = {
     1: "EnSF analysis d=2x64x64=8192, N=M_p=20, arctan obs of all components, sigma_o=0.05, K=100",
     2: "EnSF analysis d=2x128x128=32768, N=M_p=256, arctan obs of a random 25% subset, "
@@ -98,7 +98,7 @@ def run_cycle_bench(a):
     print(json.dumps(line), flush=True)
 
 
-def run_form(probs, precision, steps, warmup, dev):
+def run_form(probs, precision, steps, warmup, dev, lik_step="explicit"):
     """Times ensf_analysis (one problem) or ensf_analysis_batched (several) on `probs`."""
     import torch
     from paper_2407_12168_amd import ensf
@@ -113,7 +113,7 @@ def run_form(probs, precision, steps, warmup, dev):
         tens.append((X, post, idx, val))
         descs.append(ensf.make_problem(X, post, idx, val, p.sigma_o, p.n_steps, p.seed,
                                        p.filter_id))
-    ctx = ensf.Context(precision=precision, use_graph=True)
+    ctx = ensf.Context(precision=precision, use_graph=True, lik_step=lik_step)
     h = ctx.handle
 
     def one():
@@ -161,7 +161,7 @@ def roofline(probs, precision, phase_avg_ms, config=None):
             "phase_avg_ms": {n: round(v, 5) for n, v in zip(names, phase_avg_ms)}}
 
 
-def cpu_baseline(probs, n_sample):
+def cpu_baseline(probs, n_sample, lik_step="explicit"):
     """FP64 oracle on `n_sample` particles of the first problem, scaled to the whole job
     (cost is linear in the particle count and in each filter's N*d*K)."""
     import numpy as np
@@ -170,10 +170,11 @@ def cpu_baseline(probs, n_sample):
     from oracle import ensf as oracle_ensf
 
     p = probs[0]
+    n_sample = min(n_sample, p.n_members)
     rows = np.linspace(0, p.n_members - 1, n_sample).astype(int)
     t0 = time.perf_counter()
     oracle_ensf.analysis(p.X, p.obs_idx, p.obs_val, p.sigma_o, p.n_steps, p.seed,
-                         filter_id=p.filter_id, particle_ids=rows)
+                         filter_id=p.filter_id, particle_ids=rows, lik_step=lik_step)
     t = time.perf_counter() - t0
     work = lambda q: float(q.n_members) * q.n_members * q.dim * q.n_steps
     scale = sum(work(q) for q in probs) / (work(p) * n_sample / p.n_members)
@@ -198,7 +199,11 @@ def main():
     ap.add_argument("--other-form", default=None,
                     help="second precision reported alongside (default: the other of "
                          "fp32/bf16x3; 'none' to skip)")
-    ap.add_argument("--cpu-particles", type=int, default=16)
+    ap.add_argument("--lik-step", default="explicit", choices=("explicit", "implicit"),
+                    help="time stepping of the likelihood drift (implicit: stable at any K)")
+    ap.add_argument("--cpu-particles", type=int, default=80,
+                    help="particles of the oracle's timed sample (about 10 s at the default "
+                         "workload)")
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -219,15 +224,17 @@ def main():
     else:
         probs = [workloads.config_problem(a.config)]
     print(f"# workload: {WORKLOAD[a.config]}", file=sys.stderr, flush=True)
-    ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev)
+    ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev, a.lik_step)
     print(f"# {a.precision}: {ms:.3f} ms per analysis", file=sys.stderr, flush=True)
     other = a.other_form or ("bf16x3" if a.precision == "fp32" else "fp32")
     if other != "none":
-        ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev)
+        ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev, a.lik_step)
         print(f"# {other}: {ms2:.3f} ms per analysis", file=sys.stderr, flush=True)
     ndk = sum(p.n_members * p.dim * p.n_steps for p in probs)
     p0 = probs[0]
     cfg = {"workload": WORKLOAD[a.config], "precision": a.precision}
+    if a.lik_step != "explicit":
+        cfg["lik_step"] = a.lik_step
     if len(probs) == 1:
         cfg.update(members=p0.n_members, particles=p0.n_members, dim=p0.dim,
                    pseudo_steps=p0.n_steps, obs=int(p0.obs_idx.size))
@@ -251,7 +258,7 @@ def main():
                          "speedup_bf16x3_over_fp32":
                              (ms / ms2) if a.precision == "fp32" else (ms2 / ms)}
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(probs, a.cpu_particles)
+        line["cpu_baseline"] = cpu_baseline(probs, a.cpu_particles, a.lik_step)
     print(json.dumps(line), flush=True)
 
 

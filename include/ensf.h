@@ -65,6 +65,16 @@ typedef enum {
 
 typedef enum { ENSF_OBS_ARCTAN = 0, ENSF_OBS_LINEAR = 1 } ensf_obs_op;
 
+/* Time stepping of the reverse SDE (eq. 7) with the posterior score of eq. 17, whose
+   likelihood part is L(z) = (A_e - B_e g(z)) g'(z) per component (g the observation
+   operator, A_e = sum y / sigma_o^2, B_e = count / sigma_o^2):
+   EXPLICIT  Euler-Maruyama, z <- z - (b z - sigma^2 s) dt + sqrt(sigma^2 dt) xi;
+   IMPLICIT  the likelihood drift sigma^2 h dt L is divided by 1 + sigma^2 h dt B_e g'(z)^2
+             (linearly implicit in its Gauss-Newton curvature).  The same step without
+             observations; stable when dt is not small against sigma_o^2, where the explicit
+             step is not (it needs K of order 1 / sigma_o^2). */
+typedef enum { ENSF_LIK_EXPLICIT = 0, ENSF_LIK_IMPLICIT = 1 } ensf_lik_step;
+
 typedef struct {
   int32_t precision;      /* ensf_precision */
   int32_t obs_op;         /* ensf_obs_op */
@@ -74,6 +84,7 @@ typedef struct {
   int32_t use_graph;      /* 1: run the pseudo-time loop as a captured hipGraph */
   int32_t device;         /* HIP device ordinal the context lives on */
   const char* tune_cache; /* JSON tile-table path for the autotuner; NULL = $ENSF_TUNE_CACHE */
+  int32_t lik_step;       /* ensf_lik_step; default EXPLICIT */
 } ensf_options;
 
 /* One analysis problem of a batched call; fields as in ensf_analysis. */
@@ -92,7 +103,8 @@ typedef struct {
   uint32_t       filter_id;
 } ensf_problem;
 
-/* Fills *opt with the defaults (FP32, arctan, eps 0.05, no relaxation, graphs on, device 0). */
+/* Fills *opt with the defaults (FP32, arctan, eps 0.05, no relaxation, graphs on, device 0,
+   explicit step). */
 void ensf_default_options(ensf_options* opt);
 
 /* Creates a context on opt->device (NULL opt = defaults).  *out receives the handle.

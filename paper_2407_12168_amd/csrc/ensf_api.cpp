@@ -178,7 +178,8 @@ TileChoice heuristic_tiles(int64_t n, int64_t mp) {
 
 // Lays out one problem's workspace at offset `off` (bytes) and fills its descriptor.
 size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileChoice& tc,
-                      int obs_op, double eps, double wg_target, size_t off, char* base) {
+                      int obs_op, int lik_step, double eps, double wg_target, size_t off,
+                      char* base) {
   auto take = [&](size_t bytes) {
     off = round_up(off, kAlign);
     char* ptr = base ? base + off : nullptr;
@@ -200,6 +201,7 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.filter = p.filter_id;
   P.inv_sig2 = p.n_obs > 0 ? (float)(1.0 / ((double)p.obs_sigma * (double)p.obs_sigma)) : 0.0f;
   P.obs_op = obs_op;
+  P.lik_implicit = lik_step == ENSF_LIK_IMPLICIT ? 1 : 0;
   P.eps = eps;
   P.t_score = 1.0;
   const int bm = gram_bm(tc.gram), bn = gram_bn(tc.gram);
@@ -337,8 +339,8 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
     plan.wg_target[i] =
         std::max(8.0, 1024.0 * (double)p.n_members * p.n_particles * p.dim / total);
     ProbDev& P = plan.desc[i];
-    off = layout_problem(P, p, prec, plan.tc[i], c->opt.obs_op, c->opt.eps_alpha,
-                         plan.wg_target[i], off, nullptr);
+    off = layout_problem(P, p, prec, plan.tc[i], c->opt.obs_op, c->opt.lik_step,
+                         c->opt.eps_alpha, plan.wg_target[i], off, nullptr);
     Group& G = plan.groups[gid[f]];
     const int j = i - G.first;
     const int64_t gw = (int64_t)P.gram_tm * P.gram_tn * P.S;
@@ -361,7 +363,8 @@ void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) 
   size_t off = 0;
   for (size_t i = 0; i < plan.desc.size(); ++i)
     off = layout_problem(plan.desc[i], probs[plan.order[i]], c->opt.precision, plan.tc[i],
-                         c->opt.obs_op, c->opt.eps_alpha, plan.wg_target[i], off, c->ws);
+                         c->opt.obs_op, c->opt.lik_step, c->opt.eps_alpha, plan.wg_target[i],
+                         off, c->ws);
 }
 
 struct Uploaded {
@@ -660,6 +663,7 @@ void ensf_default_options(ensf_options* opt) {
   if (!opt) return;
   opt->precision = ENSF_PREC_FP32;
   opt->obs_op = ENSF_OBS_ARCTAN;
+  opt->lik_step = ENSF_LIK_EXPLICIT;
   opt->eps_alpha = 0.05;
   opt->spread_relax = 0.0;
   opt->use_graph = 1;
@@ -673,7 +677,9 @@ ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out) {
   ensf_options o;
   ensf_default_options(&o);
   if (opt) o = *opt;
-  if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1) return ENSF_EINVAL;
+  if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1 || o.lik_step < 0 ||
+      o.lik_step > 1)
+    return ENSF_EINVAL;
   if (!(o.eps_alpha > 0.0 && o.eps_alpha < 1.0)) return ENSF_EINVAL;
   if (!(o.spread_relax >= 0.0 && o.spread_relax <= 1.0)) return ENSF_EINVAL;
   int ndev = 0;

@@ -43,6 +43,7 @@ struct ProbDev {
   uint32_t seed_lo, seed_hi, filter;
   float inv_sig2;
   int32_t obs_op;
+  int32_t lik_implicit;     // 1: linearly implicit likelihood drift in the update
   double eps, t_score;
   int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
   int32_t wx_tp, wx_te;       // W.X tiles along particles, state components
@@ -51,6 +52,7 @@ struct ProbDev {
 // Per-step scalars in FP32, computed in FP64 from (t, eps) exactly as the oracle does.
 struct StepScalars {
   float alpha, inv_beta2, b, sigma2, h, dt, cnoise;
+  float damp;   // sigma^2 h dt: weight of the likelihood score in the update
 };
 
 // Prefix arrays of a grouped launch: tiles of problem f are [pre[f], pre[f+1]).

@@ -72,6 +72,7 @@ __device__ __forceinline__ StepScalars step_scalars(double t, double eps, int K)
   s.h = (float)(1.0 - t);
   s.dt = (float)dt;
   s.cnoise = (float)sqrt(sigma2 * dt);
+  s.damp = (float)(sigma2 * (1.0 - t) * dt);
   return s;
 }
 
@@ -132,17 +133,30 @@ __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
 }
 
 // Damped posterior score (eq. 17) of one component given xhat = sum_j w_j x_j.
-__device__ __forceinline__ float posterior_score(float z, float xh, float a, float b,
+// a_e = sum y / sigma_o^2 and b_e = count / sigma_o^2 of the component (eq. 5).
+__device__ __forceinline__ float posterior_score(float z, float xh, float a_e, float b_e,
                                                  const StepScalars& sc, int op) {
   const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
-  const float lik = (op == kArctan) ? (a - b * atanf(z)) * __builtin_amdgcn_rcpf(1.0f + z * z)
-                                    : (a - b * z);
+  const float lik = (op == kArctan)
+                        ? (a_e - b_e * atanf(z)) * __builtin_amdgcn_rcpf(1.0f + z * z)
+                        : (a_e - b_e * z);
   return prior + sc.h * lik;
 }
 
-// Euler-Maruyama step of the reverse-time SDE (eq. 7), backward in t.
-__device__ __forceinline__ float em_step(float z, float s, float xi, const StepScalars& sc) {
-  return z - (sc.b * z - sc.sigma2 * s) * sc.dt + sc.cnoise * xi;
+// One step of the reverse-time SDE (eq. 7), backward in t, with the posterior score of
+// eq. 17 split into its prior part and its likelihood part L = (A - B g(z)) g'(z).
+// Explicit (Euler-Maruyama):  z - (b z - sigma^2 prior) dt + sigma^2 h dt L + c xi.
+// Linearly implicit likelihood: the L term is divided by 1 + sigma^2 h dt kappa with the
+// Gauss-Newton curvature kappa = B g'(z)^2, which keeps the step stable when dt is not
+// small against sigma_o^2; without observations (B = 0) both are the same step.
+__device__ __forceinline__ float update_step(float z, float xh, float a_e, float b_e, float xi,
+                                             const StepScalars& sc, int op, bool implicit) {
+  const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
+  const float gp = (op == kArctan) ? __builtin_amdgcn_rcpf(1.0f + z * z) : 1.0f;
+  const float lik = (op == kArctan) ? (a_e - b_e * atanf(z)) * gp : (a_e - b_e * z);
+  float w = sc.damp;
+  if (implicit) w *= __builtin_amdgcn_rcpf(1.0f + sc.damp * b_e * gp * gp);
+  return z - (sc.b * z - sc.sigma2 * prior) * sc.dt + w * lik + sc.cnoise * xi;
 }
 
 // ----------------------------------------------------------------------------------------
@@ -673,6 +687,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
   float* const So = P.score_out;
   const int64_t dd = P.d, ldz = P.ldz, Mp = P.Mp;
   const int obs_op = P.obs_op;
+  const bool implicit = P.lik_implicit != 0;
   const uint32_t filt = P.filter, k0 = P.seed_lo, k1 = P.seed_hi;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
@@ -693,12 +708,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
         const f32x4 z = gload(zp);
         const f32x4 av = gload(reinterpret_cast<const f32x4*>(Ap + e));
         const f32x4 bv = gload(reinterpret_cast<const f32x4*>(Bp + e));
-        const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, obs_op);
-        const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, obs_op);
-        const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, obs_op);
-        const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, obs_op);
         const int64_t rem = dd - e;
         if constexpr (SCORE) {
+          const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, obs_op);
+          const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, obs_op);
+          const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, obs_op);
+          const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, obs_op);
           float* so = So + i * dd + e;
           so[0] = s0;
           if (rem > 1) so[1] = s1;
@@ -711,10 +726,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
           box_muller(w.w0, w.w1, n0, n1);
           box_muller(w.w2, w.w3, n2, n3);
           f32x4 zn;
-          zn.x = em_step(z.x, s0, n0, sc);
-          zn.y = em_step(z.y, s1, n1, sc);
-          zn.z = em_step(z.z, s2, n2, sc);
-          zn.w = em_step(z.w, s3, n3, sc);
+          zn.x = update_step(z.x, xh0, av.x, bv.x, n0, sc, obs_op, implicit);
+          zn.y = update_step(z.y, xh1, av.y, bv.y, n1, sc, obs_op, implicit);
+          zn.z = update_step(z.z, xh2, av.z, bv.z, n2, sc, obs_op, implicit);
+          zn.w = update_step(z.w, xh3, av.w, bv.w, n3, sc, obs_op, implicit);
           if (rem < 4) {  // ragged tail: keep the padding at zero
             zn.w = 0.0f;
             if (rem < 3) zn.z = 0.0f;

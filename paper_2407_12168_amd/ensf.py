@@ -16,6 +16,7 @@ DEFAULT_TUNE_CACHE = os.path.join(HERE, "tune_gfx950.json")
 ENSF_OK, ENSF_EINVAL, ENSF_ENOMEM, ENSF_EHIP, ENSF_ENONFINITE, ENSF_EUNSUPPORTED = range(6)
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "bf16": 2}
 OBS_OPS = {"arctan": 0, "linear": 1}
+LIK_STEPS = {"explicit": 0, "implicit": 1}
 INIT_STEP = 0xFFFFFFFF
 
 
@@ -32,7 +33,7 @@ class ensf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("obs_op", ctypes.c_int32),
                 ("eps_alpha", ctypes.c_double), ("spread_relax", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("lik_step", ctypes.c_int32)]
 
 
 class ensf_problem(ctypes.Structure):
@@ -47,8 +48,8 @@ class ensf_problem(ctypes.Structure):
 _LIB = None
 EXPORTS = ("ensf_default_options", "ensf_create", "ensf_analysis", "ensf_analysis_batched",
            "ensf_score", "ensf_rng_normal", "ensf_ensemble_stats", "ensf_sync_status",
-           "ensf_autotune", "ensf_autotune_batched", "ensf_profile_phases", "ensf_phase_times", "ensf_destroy",
-           "ensf_status_string", "ensf_last_error_string")
+           "ensf_autotune", "ensf_autotune_batched", "ensf_profile_phases", "ensf_phase_times",
+           "ensf_destroy", "ensf_status_string", "ensf_last_error_string")
 
 
 def _lib():
@@ -129,7 +130,7 @@ def ensf_default_options():
 
 
 def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=0.0,
-                use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE):
+                use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE, lik_step="explicit"):
     o = ensf_default_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
@@ -138,6 +139,7 @@ def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=
     o.use_graph = 1 if use_graph else 0
     o.device = device
     o.tune_cache = tune_cache.encode() if tune_cache else None
+    o.lik_step = LIK_STEPS[lik_step] if isinstance(lik_step, str) else int(lik_step)
     h = ctypes.c_void_p()
     _check(_lib().ensf_create(ctypes.byref(o), ctypes.byref(h)), "ensf_create")
     return h
