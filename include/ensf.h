@@ -161,7 +161,9 @@ ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count);
    scale, k-step depth and LDS stage count with the W.X variant fixed, then the W.X tile,
    k-step depth and stage count, then the Gram side again.  Cache entries map a key
    "gfx950/p<precision>/n<log2 N>/m<log2 M_p>/d<log2 d>" to
-   [gram tile, W.X tile, split scale, Gram k-step, W.X k-step, Gram stages, W.X stages]. */
+   [gram tile, W.X tile, split scale, Gram k-step, W.X k-step, Gram stages, W.X stages].
+   With the environment variable ENSF_TUNE_LOG set, each timed candidate is reported on
+   stderr. */
 ensf_status ensf_autotune(ensf_ctx* ctx, const ensf_problem* prob, void* stream);
 
 /* The same for a batch (an array of n_problems host descriptors, as for

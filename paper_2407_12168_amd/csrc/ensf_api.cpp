@@ -635,7 +635,8 @@ void load_tune_cache(ensf_ctx* c) {
     auto ok_bk = [](int v) { return v == 32 || v == 64; };
     auto ok_st = [](int v) { return v == 1 || v == 2; };
     if (got >= 3 && tc.gram >= 0 && tc.gram < kNumGram && tc.wx >= 0 && tc.wx < kNumWx &&
-        ok_bk(tc.gram_bk) && ok_bk(tc.wx_bk) && ok_st(tc.gram_st) && ok_st(tc.wx_st))
+        ok_bk(tc.gram_bk) && ok_bk(tc.wx_bk) && ok_st(tc.gram_st) && ok_st(tc.wx_st) &&
+        gram_variant_exists(tc.gram, tc.gram_bk))
       c->tune[key] = tc;
     pos = end + 1;
   }
@@ -815,6 +816,8 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, i
   HIP_TRY(hipEventCreate(&e1));
   const int use_graph = ctx->opt.use_graph;
   ctx->opt.use_graph = 0;
+  // ENSF_TUNE_LOG set: one line per timed candidate on stderr.
+  const bool log = getenv("ENSF_TUNE_LOG") != nullptr;
   // Time of one candidate: two timed analyses after a warm-up.
   auto time_of = [&](const TileChoice& tc, float& ms_sum) {
     ms_sum = 0.0f;
@@ -829,6 +832,10 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, i
       if (st == ENSF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = ENSF_EHIP;
       ms_sum += ms;
     }
+    if (log && st == ENSF_OK)
+      fprintf(stderr, "ensf_autotune: gram %d/%d/%d split %.2f wx %d/%d/%d: %.3f ms\n", tc.gram,
+              tc.gram_bk, tc.gram_st, tc.split_scale, tc.wx, tc.wx_bk, tc.wx_st, ms_sum / 2);
+    if (log) fflush(stderr);
     return st == ENSF_OK;
   };
   // Coordinate search: the Gram side (tile, split-K scale, k-step, stages) with the W.X
@@ -843,6 +850,7 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, i
         for (double sc : scales)
           for (int bk : {32, 64})
             for (int ns : {1, 2}) {
+              if (!gram_variant_exists(gc, bk)) continue;
               TileChoice tc = base;
               tc.gram = gc;
               tc.split_scale = sc;

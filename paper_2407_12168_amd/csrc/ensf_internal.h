@@ -65,17 +65,39 @@ struct GroupedLaunch {
 
 // Kernel-shape identifiers chosen by the host (heuristic or autotuner).
 // Gram tiles: particles x members.
-enum GramCfg : int { kGram128 = 0, kGram64 = 1, kGram32 = 2, kGram256 = 3, kNumGram = 4 };
+enum GramCfg : int {
+  kGram128 = 0, kGram64 = 1, kGram32 = 2, kGram256 = 3,
+  kGram256x256 = 4,   // 4 waves of 128 x 128
+  kGram256w = 5,      // 256 x 128 on 4 waves of 128 x 64
+  kNumGram = 6
+};
 // W.X tiles: state components x particles.
-enum WxCfg : int { kWx128 = 0, kWx64 = 1, kWx32 = 2, kWx256 = 3, kWx128x256 = 4, kNumWx = 5 };
+enum WxCfg : int {
+  kWx128 = 0, kWx64 = 1, kWx32 = 2, kWx256 = 3, kWx128x256 = 4,
+  kWx256w = 5,        // 256 x 128 on 4 waves of 128 x 64
+  kWx128x256w = 6,    // 128 x 256 on 4 waves of 64 x 128
+  kNumWx = 7
+};
 
 // kGram256 is 256 particles x 128 members; kWx256 is 256 components x 128 particles.
-inline int gram_bm(int c) { return c == kGram256 ? 256 : c == kGram128 ? 128 : c == kGram64 ? 64 : 32; }
-inline int gram_bn(int c) { return c == kGram256 ? 128 : gram_bm(c); }
-inline int wx_be(int c) { return c == kWx256 ? 256 : 128; }
-inline int wx_bp(int c) {
-  return c == kWx128x256 ? 256 : c == kWx128 || c == kWx256 ? 128 : c == kWx64 ? 64 : 32;
+inline int gram_bm(int c) {
+  return c == kGram256 || c == kGram256x256 || c == kGram256w ? 256
+         : c == kGram128                                    ? 128
+         : c == kGram64                                     ? 64
+                                                            : 32;
 }
+inline int gram_bn(int c) {
+  return c == kGram256x256 ? 256 : c == kGram256 || c == kGram256w ? 128 : gram_bm(c);
+}
+inline int wx_be(int c) { return c == kWx256 || c == kWx256w ? 256 : 128; }
+inline int wx_bp(int c) {
+  return c == kWx128x256 || c == kWx128x256w     ? 256
+         : c == kWx128 || c == kWx256 || c == kWx256w ? 128
+         : c == kWx64                              ? 64
+                                                   : 32;
+}
+// kGram256x256 exists with a k-step of 32 only (at 64 its split-BF16 form spills).
+inline bool gram_variant_exists(int cfg, int bk) { return !(cfg == kGram256x256 && bk == 64); }
 // k-step depths of the MFMA main loops are template variants (32 or 64); every padding
 // is a multiple of the largest.  The LDS stage count (1, or 2 = ping-pong) is a variant too.
 constexpr int kMaxBK = 64;

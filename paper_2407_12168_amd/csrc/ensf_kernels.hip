@@ -905,11 +905,23 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
     return hipGetLastError();                                                                \
   }
 
+#define ENSF_GRAM_CASE32(PR, C, WGM, WGN, TM, TN)                                            \
+  if (prec == PR && cfg == C) {                                                              \
+    if (bk != 32) return hipErrorInvalidValue;                                               \
+    if (st == 2)                                                                             \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 32, 2);                                         \
+    else                                                                                     \
+      ENSF_GRAM_LAUNCH(PR, WGM, WGN, TM, TN, 32, 1);                                         \
+    return hipGetLastError();                                                                \
+  }
+
 #define ENSF_GRAM_ALL(PR)                 \
   ENSF_GRAM_CASE(PR, kGram128, 2, 2, 2, 2) \
   ENSF_GRAM_CASE(PR, kGram64, 2, 2, 1, 1)  \
   ENSF_GRAM_CASE(PR, kGram32, 1, 1, 1, 1)  \
-  ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)
+  ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)    \
+  ENSF_GRAM_CASE32(PR, kGram256x256, 2, 2, 4, 4) \
+  ENSF_GRAM_CASE(PR, kGram256w, 2, 2, 4, 2)
 
 hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g, int step,
                        hipStream_t s) {
@@ -938,13 +950,16 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
     return hipGetLastError();                                                                \
   }
 
-// (components x particles) per config: 128x128, 128x64, 128x32, 256x128, 128x256
+// (components x particles) per config: 128x128, 128x64, 128x32, 256x128, 128x256, then
+// 256x128 and 128x256 on four waves with larger per-wave tiles
 #define ENSF_WX_ALL(PR)                     \
   ENSF_WX_CASE(PR, kWx128, 2, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx64, 2, 2, 2, 1)       \
   ENSF_WX_CASE(PR, kWx32, 4, 1, 1, 1)       \
   ENSF_WX_CASE(PR, kWx256, 4, 2, 2, 2)      \
-  ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)
+  ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)  \
+  ENSF_WX_CASE(PR, kWx256w, 2, 2, 4, 2)     \
+  ENSF_WX_CASE(PR, kWx128x256w, 2, 2, 2, 4)
 
 hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
                      int step, unsigned long long* nonfinite, hipStream_t s) {
