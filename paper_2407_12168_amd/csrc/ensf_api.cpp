@@ -649,9 +649,9 @@ void save_tune_cache(ensf_ctx* c) {
   fprintf(fp, "{\n");
   size_t i = 0;
   for (const auto& kv : c->tune)
-    fprintf(fp, "  \"%s\": [%d, %d, %.3f, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.gram,
-            kv.second.wx, kv.second.split_scale, kv.second.gram_bk, kv.second.wx_bk,
-            kv.second.gram_st, kv.second.wx_st, ++i < c->tune.size() ? "," : "");
+    fprintf(fp, "  \"%s\": [%d, %d, %.3f, %d, %d, %d, %d]%s\n", kv.first.c_str(),
+            kv.second.gram, kv.second.wx, kv.second.split_scale, kv.second.gram_bk,
+            kv.second.wx_bk, kv.second.gram_st, kv.second.wx_st, ++i < c->tune.size() ? "," : "");
   fprintf(fp, "}\n");
   fclose(fp);
 }
@@ -833,8 +833,9 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, i
       ms_sum += ms;
     }
     if (log && st == ENSF_OK)
-      fprintf(stderr, "ensf_autotune: gram %d/%d/%d split %.2f wx %d/%d/%d: %.3f ms\n", tc.gram,
-              tc.gram_bk, tc.gram_st, tc.split_scale, tc.wx, tc.wx_bk, tc.wx_st, ms_sum / 2);
+      fprintf(stderr, "ensf_autotune: gram %d/%d/%d split %.2f wx %d/%d/%d: %.3f ms\n",
+              tc.gram, tc.gram_bk, tc.gram_st, tc.split_scale, tc.wx, tc.wx_bk, tc.wx_st,
+              ms_sum / 2);
     if (log) fflush(stderr);
     return st == ENSF_OK;
   };

@@ -134,13 +134,16 @@ __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
 
 // Damped posterior score (eq. 17) of one component given xhat = sum_j w_j x_j.
 // a_e = sum y / sigma_o^2 and b_e = count / sigma_o^2 of the component (eq. 5).
+// The fused multiply-adds of the score and the update are written out and the compiler may
+// fuse nothing else, so every kernel that inlines them computes the same bits.
 __device__ __forceinline__ float posterior_score(float z, float xh, float a_e, float b_e,
                                                  const StepScalars& sc, int op) {
-  const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
+#pragma clang fp contract(off)
+  const float prior = fmaf(sc.alpha, xh, -z) * sc.inv_beta2;
   const float lik = (op == kArctan)
-                        ? (a_e - b_e * atanf(z)) * __builtin_amdgcn_rcpf(1.0f + z * z)
-                        : (a_e - b_e * z);
-  return prior + sc.h * lik;
+                        ? fmaf(-b_e, atanf(z), a_e) * __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f))
+                        : fmaf(-b_e, z, a_e);
+  return fmaf(sc.h, lik, prior);
 }
 
 // One step of the reverse-time SDE (eq. 7), backward in t, with the posterior score of
@@ -151,12 +154,16 @@ __device__ __forceinline__ float posterior_score(float z, float xh, float a_e, f
 // small against sigma_o^2; without observations (B = 0) both are the same step.
 __device__ __forceinline__ float update_step(float z, float xh, float a_e, float b_e, float xi,
                                              const StepScalars& sc, int op, bool implicit) {
-  const float prior = -(z - sc.alpha * xh) * sc.inv_beta2;
-  const float gp = (op == kArctan) ? __builtin_amdgcn_rcpf(1.0f + z * z) : 1.0f;
-  const float lik = (op == kArctan) ? (a_e - b_e * atanf(z)) * gp : (a_e - b_e * z);
+#pragma clang fp contract(off)
+  const float prior = fmaf(sc.alpha, xh, -z) * sc.inv_beta2;
+  const float gp = (op == kArctan) ? __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f)) : 1.0f;
+  const float lik = (op == kArctan) ? fmaf(-b_e, atanf(z), a_e) * gp : fmaf(-b_e, z, a_e);
   float w = sc.damp;
-  if (implicit) w *= __builtin_amdgcn_rcpf(1.0f + sc.damp * b_e * gp * gp);
-  return z - (sc.b * z - sc.sigma2 * prior) * sc.dt + w * lik + sc.cnoise * xi;
+  if (implicit) w *= __builtin_amdgcn_rcpf(fmaf((sc.damp * b_e) * gp, gp, 1.0f));
+  const float drift = fmaf(sc.b, z, -(sc.sigma2 * prior));   // b z - sigma^2 prior
+  float out = fmaf(-drift, sc.dt, z);
+  out = fmaf(w, lik, out);
+  return fmaf(sc.cnoise, xi, out);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -615,6 +622,88 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
 // holds four consecutive components of one particle, i.e. exactly the four normals of one
 // Philox counter, so the epilogue runs from the accumulators without any exchange.
 
+// Epilogue state of one W.X tile: descriptor fields and step scalars in registers.
+struct WxEpi {
+  float* Z;
+  const float* A;
+  const float* B;
+  float* score_out;
+  int64_t d, ldz, Mp, i0, e0;
+  StepScalars sc;
+  int obs_op, step;
+  bool implicit, active;
+  uint32_t filt, k0, k1;
+};
+
+__device__ __forceinline__ WxEpi make_wx_epi(const ProbDev& P, int step, int64_t i0, int64_t e0,
+                                             bool active) {
+  WxEpi E;
+  E.Z = P.Z;
+  E.A = P.A;
+  E.B = P.B;
+  E.score_out = P.score_out;
+  E.d = P.d;
+  E.ldz = P.ldz;
+  E.Mp = P.Mp;
+  E.i0 = i0;
+  E.e0 = e0;
+  E.sc = step_scalars(step_time(P, step), P.eps, P.K);
+  E.obs_op = P.obs_op;
+  E.step = step;
+  E.implicit = P.lik_implicit != 0;
+  E.active = active;
+  E.filt = P.filter;
+  E.k0 = P.seed_lo;
+  E.k1 = P.seed_hi;
+  return E;
+}
+
+// One accumulator quad of a lane: block (a, b), register group gq, i.e. xhat for four
+// consecutive components e..e+3 of particle i (one Philox counter).  SCORE writes the
+// posterior score; otherwise the particle components are advanced one step in place.
+template <int WGN, int TM, int TN, bool SCORE>
+__device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc)[TM][TN], int a,
+                                            int b, int gq, unsigned int& bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int64_t i = E.i0 + wn * TN * 32 + b * 32 + (lane & 31);
+  const int64_t e = E.e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+  if (i >= E.Mp || e >= E.d) return;
+  const float xh0 = acc[a][b][gq * 4 + 0], xh1 = acc[a][b][gq * 4 + 1];
+  const float xh2 = acc[a][b][gq * 4 + 2], xh3 = acc[a][b][gq * 4 + 3];
+  f32x4* zp = reinterpret_cast<f32x4*>(E.Z + i * E.ldz + e);
+  const f32x4 z = gload(zp);
+  const f32x4 av = gload(reinterpret_cast<const f32x4*>(E.A + e));
+  const f32x4 bv = gload(reinterpret_cast<const f32x4*>(E.B + e));
+  const int64_t rem = E.d - e;
+  if constexpr (SCORE) {
+    float* so = E.score_out + i * E.d + e;
+    so[0] = posterior_score(z.x, xh0, av.x, bv.x, E.sc, E.obs_op);
+    if (rem > 1) so[1] = posterior_score(z.y, xh1, av.y, bv.y, E.sc, E.obs_op);
+    if (rem > 2) so[2] = posterior_score(z.z, xh2, av.z, bv.z, E.sc, E.obs_op);
+    if (rem > 3) so[3] = posterior_score(z.w, xh3, av.w, bv.w, E.sc, E.obs_op);
+  } else {
+    const Words4 w =
+        philox4x32_10((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)E.step, E.filt, E.k0, E.k1);
+    float n0, n1, n2, n3;
+    box_muller(w.w0, w.w1, n0, n1);
+    box_muller(w.w2, w.w3, n2, n3);
+    f32x4 zn;
+    zn.x = update_step(z.x, xh0, av.x, bv.x, n0, E.sc, E.obs_op, E.implicit);
+    zn.y = update_step(z.y, xh1, av.y, bv.y, n1, E.sc, E.obs_op, E.implicit);
+    zn.z = update_step(z.z, xh2, av.z, bv.z, n2, E.sc, E.obs_op, E.implicit);
+    zn.w = update_step(z.w, xh3, av.w, bv.w, n3, E.sc, E.obs_op, E.implicit);
+    if (rem < 4) {  // ragged tail: keep the padding at zero
+      zn.w = 0.0f;
+      if (rem < 3) zn.z = 0.0f;
+      if (rem < 2) zn.y = 0.0f;
+    }
+    if (!isfinite(zn.x + zn.y + zn.z + zn.w))
+      bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
+    gstore(zp, zn);
+  }
+}
+
 template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
@@ -679,69 +768,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
         acc);
   }
 
-  const StepScalars sc = step_scalars(step_time(P, step), P.eps, P.K);
-  // descriptor fields in registers for the epilogue
-  float* const Zp = P.Z;
-  const float* const Ap = P.A;
-  const float* const Bp = P.B;
-  float* const So = P.score_out;
-  const int64_t dd = P.d, ldz = P.ldz, Mp = P.Mp;
-  const int obs_op = P.obs_op;
-  const bool implicit = P.lik_implicit != 0;
-  const uint32_t filt = P.filter, k0 = P.seed_lo, k1 = P.seed_hi;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
+  const WxEpi E = make_wx_epi(P, step, i0, e0, true);
   unsigned int bad = 0;
 #pragma unroll
-  for (int b = 0; b < TN; ++b) {
-    const int64_t i = i0 + wn * TN * 32 + b * 32 + (lane & 31);
-    if (i >= Mp) continue;
+  for (int b = 0; b < TN; ++b)
 #pragma unroll
-    for (int a = 0; a < TM; ++a) {
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int gq = 0; gq < 4; ++gq) {
-        const int64_t e = e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
-        if (e >= dd) continue;
-        const float xh0 = acc[a][b][gq * 4 + 0], xh1 = acc[a][b][gq * 4 + 1];
-        const float xh2 = acc[a][b][gq * 4 + 2], xh3 = acc[a][b][gq * 4 + 3];
-        f32x4* zp = reinterpret_cast<f32x4*>(Zp + i * ldz + e);
-        const f32x4 z = gload(zp);
-        const f32x4 av = gload(reinterpret_cast<const f32x4*>(Ap + e));
-        const f32x4 bv = gload(reinterpret_cast<const f32x4*>(Bp + e));
-        const int64_t rem = dd - e;
-        if constexpr (SCORE) {
-          const float s0 = posterior_score(z.x, xh0, av.x, bv.x, sc, obs_op);
-          const float s1 = posterior_score(z.y, xh1, av.y, bv.y, sc, obs_op);
-          const float s2 = posterior_score(z.z, xh2, av.z, bv.z, sc, obs_op);
-          const float s3 = posterior_score(z.w, xh3, av.w, bv.w, sc, obs_op);
-          float* so = So + i * dd + e;
-          so[0] = s0;
-          if (rem > 1) so[1] = s1;
-          if (rem > 2) so[2] = s2;
-          if (rem > 3) so[3] = s3;
-        } else {
-          const Words4 w = philox4x32_10((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)step, filt,
-                                         k0, k1);
-          float n0, n1, n2, n3;
-          box_muller(w.w0, w.w1, n0, n1);
-          box_muller(w.w2, w.w3, n2, n3);
-          f32x4 zn;
-          zn.x = update_step(z.x, xh0, av.x, bv.x, n0, sc, obs_op, implicit);
-          zn.y = update_step(z.y, xh1, av.y, bv.y, n1, sc, obs_op, implicit);
-          zn.z = update_step(z.z, xh2, av.z, bv.z, n2, sc, obs_op, implicit);
-          zn.w = update_step(z.w, xh3, av.w, bv.w, n3, sc, obs_op, implicit);
-          if (rem < 4) {  // ragged tail: keep the padding at zero
-            zn.w = 0.0f;
-            if (rem < 3) zn.z = 0.0f;
-            if (rem < 2) zn.y = 0.0f;
-          }
-          if (!isfinite(zn.x + zn.y + zn.z + zn.w))
-            bad += !isfinite(zn.x) + !isfinite(zn.y) + !isfinite(zn.z) + !isfinite(zn.w);
-          gstore(zp, zn);
-        }
-      }
-    }
-  }
+      for (int gq = 0; gq < 4; ++gq) wx_epi_quad<WGN, TM, TN, SCORE>(E, acc, a, b, gq, bad);
   if (!SCORE && bad) atomicAdd(nonfinite, (unsigned long long)bad);
 }
 
