@@ -176,13 +176,24 @@ template <int PREC, int BM, int BN, int BK>
 struct TileSmem {
   // FP32 operands are stored k-major ([k][row]) so that a lane's single value per MFMA is
   // read from consecutive addresses; BF16 operands row-major ([row][k]) so a lane reads
-  // its 8 consecutive k values as one 16-byte access.
+  // its 8 consecutive k values as one 16-byte access.  BF16 rows are not padded: their
+  // 16-byte chunks are permuted by bf16_chunk_swizzle instead.
   static constexpr int LDF_A = BM + 4, LDF_B = BN + 4;
-  static constexpr int LDH = BK + 8;
+  static constexpr int LDH = BK;
   static constexpr int kFp32Bytes = BK * (LDF_A + LDF_B) * 4;
   static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * 2;
   static constexpr int kBytes = PREC == kFP32 ? kFp32Bytes : kBf16Bytes;
 };
+
+// Element offset, within row r of a BF16 LDS tile with BK elements per row, of the row's
+// 16-byte chunk `chunk` (8 elements).  Chunks are XOR-permuted by the row's position among
+// the 256-byte bank spans: a quarter-wave reading one chunk of 16 consecutive rows, and a
+// half-wave writing whole consecutive rows, then touch every bank once.
+template <int BK>
+__device__ __forceinline__ int bf16_chunk_swizzle(int r, int chunk) {
+  constexpr int kChunks = BK / 8, kRowsPerSpan = 128 / BK;
+  return (chunk ^ ((r / kRowsPerSpan) & (kChunks - 1))) * 8;
+}
 
 template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&acc)[TM][TN]) {
@@ -216,18 +227,20 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
-      const int ko = kk + (lane >> 5) * 8;
+      const int kc = kk / 8 + (lane >> 5);   // 16-byte chunk of the row
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
         const int r = wm * TM * 32 + tm * 32 + (lane & 31);
-        ah[tm] = *reinterpret_cast<const bf16x8_t*>(sAh + r * S::LDH + ko);
-        if constexpr (PREC == kBF16X3) al[tm] = *reinterpret_cast<const bf16x8_t*>(sAl + r * S::LDH + ko);
+        const int o = r * S::LDH + bf16_chunk_swizzle<BK>(r, kc);
+        ah[tm] = *reinterpret_cast<const bf16x8_t*>(sAh + o);
+        if constexpr (PREC == kBF16X3) al[tm] = *reinterpret_cast<const bf16x8_t*>(sAl + o);
       }
 #pragma unroll
       for (int tn = 0; tn < TN; ++tn) {
         const int r = wn * TN * 32 + tn * 32 + (lane & 31);
-        bh[tn] = *reinterpret_cast<const bf16x8_t*>(sBh + r * S::LDH + ko);
-        if constexpr (PREC == kBF16X3) bl[tn] = *reinterpret_cast<const bf16x8_t*>(sBl + r * S::LDH + ko);
+        const int o = r * S::LDH + bf16_chunk_swizzle<BK>(r, kc);
+        bh[tn] = *reinterpret_cast<const bf16x8_t*>(sBh + o);
+        if constexpr (PREC == kBF16X3) bl[tn] = *reinterpret_cast<const bf16x8_t*>(sBl + o);
       }
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
@@ -351,7 +364,8 @@ struct F32KmajLoad {
       uint32_t h01, l01, h23, l23;
       split_pair(f32x2{v[it].x, v[it].y}, h01, l01);
       split_pair(f32x2{v[it].z, v[it].w}, h23, l23);
-      const int o = (r + it * kRowStep) * lds + c * 4;
+      const int row = r + it * kRowStep;   // c: 8-byte half c % 2 of 16-byte chunk c / 2
+      const int o = row * lds + bf16_chunk_swizzle<BK>(row, c >> 1) + (c & 1) * 4;
       *reinterpret_cast<u32x2*>(sh + o) = u32x2{h01, h23};
       if constexpr (LO) *reinterpret_cast<u32x2*>(sl + o) = u32x2{l01, l23};
     }
@@ -416,7 +430,8 @@ struct Bf16KmajLoad {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
       if (kVec % NT == 0 || (int)threadIdx.x + it * NT < kVec) {
-        const int o = (r + it * kRowStep) * lds + c * 8;
+        const int row = r + it * kRowStep;
+        const int o = row * lds + bf16_chunk_swizzle<BK>(row, c);
         *reinterpret_cast<u32x4*>(sh + o) = h[it];
         if constexpr (LO) *reinterpret_cast<u32x4*>(sl + o) = l[it];
       }

@@ -111,3 +111,34 @@ def test_implicit_equals_explicit_without_observations(dev):
 def test_invalid_lik_step_rejected(dev):
     with pytest.raises(ensf.EnsfError):
         ensf.Context(lik_step=2)
+
+
+def test_literal_k_config4_full_batch_sampled(dev):
+    # all 64 filters in one batched call, the tuned launch configuration the benchmark
+    # times; three filters (largest, smallest, a middle one) checked on two particles each
+    probs = workloads.batched_problems(n_filters=64, n_steps=100, sigma_o=0.05)
+    tens, descs = [], []
+    for p in probs:
+        X = torch.from_numpy(p.X).to(dev)
+        post = torch.empty_like(X)
+        idx = torch.from_numpy(p.obs_idx).to(dev)
+        val = torch.from_numpy(p.obs_val).to(dev)
+        tens.append((X, post, idx, val))
+        descs.append(ensf.make_problem(X, post, idx, val, p.sigma_o, p.n_steps, p.seed,
+                                       p.filter_id))
+    with ensf.Context(precision="bf16x3", lik_step="implicit") as ctx:
+        ensf.ensf_analysis_batched(ctx.handle, descs)
+        st, nbad = ensf.ensf_sync_status(ctx.handle)
+    assert st == ensf.ENSF_OK, (st, nbad)
+    work = [p.n_members ** 2 * p.dim for p in probs]
+    order = np.argsort(work)
+    for f in (order[-1], order[0], order[len(order) // 2]):
+        p = probs[f]
+        rows = [0, p.n_members - 1]
+        got = tens[f][1][rows].cpu().numpy().astype(np.float64)
+        want = O.analysis(p.X, p.obs_idx, p.obs_val, p.sigma_o, p.n_steps, p.seed,
+                          filter_id=p.filter_id, particle_ids=rows, lik_step="implicit",
+                          chunk=2)
+        err = O.rel_l2(got, want)
+        print(f"c4 filter {f} (N={p.n_members}, d={p.dim}) particles {rows}: rel-L2 {err:.2e}")
+        assert err <= 1e-3
