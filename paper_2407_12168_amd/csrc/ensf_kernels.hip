@@ -172,52 +172,82 @@ __device__ __forceinline__ float update_step(float z, float xh, float a_e, float
 // 32x32 accumulator layout (both MFMA kinds): lane l, register r holds
 // row (r/4)*8 + (l/32)*4 + r%4, column l%32.
 
-template <int PREC, int BM, int BN, int BK>
+// LDS tile of the A (BM rows) and B (BN rows) operands of one k-step of BK.  Operands are
+// row-major ([row][k], unpadded, 16-byte chunks permuted by chunk_swizzle) so that a lane
+// reads consecutive k values of its row as one 16-byte access: 8 values (BF16) or 4 (FP32).
+// AK: the FP32 A operand is k-major instead ([k][row], rows padded to BM + 8 floats, which
+// puts the k-rows read by the two half-waves in opposite halves of the banks); used where
+// the operand's rows are contiguous in global memory (X in W.X).
+template <int PREC, int BM, int BN, int BK, bool AK = false>
 struct TileSmem {
-  // FP32 operands are stored k-major ([k][row]) so that a lane's single value per MFMA is
-  // read from consecutive addresses; BF16 operands row-major ([row][k]) so a lane reads
-  // its 8 consecutive k values as one 16-byte access.  BF16 rows are not padded: their
-  // 16-byte chunks are permuted by bf16_chunk_swizzle instead.
-  static constexpr int LDF_A = BM + 4, LDF_B = BN + 4;
-  static constexpr int LDH = BK;
-  static constexpr int kFp32Bytes = BK * (LDF_A + LDF_B) * 4;
+  static constexpr int LDF_A = BM + 8;                      // k-major FP32 A
+  static constexpr int LDH = BK;                            // row-major rows (elements)
+  static constexpr int kAFloats = AK ? BK * LDF_A : BM * BK;
+  static constexpr int kFp32Bytes = (kAFloats + BN * BK) * 4;
   static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * 2;
   static constexpr int kBytes = PREC == kFP32 ? kFp32Bytes : kBf16Bytes;
 };
 
-// Element offset, within row r of a BF16 LDS tile with BK elements per row, of the row's
-// 16-byte chunk `chunk` (8 elements).  Chunks are XOR-permuted by the row's position among
-// the 256-byte bank spans: a quarter-wave reading one chunk of 16 consecutive rows, and a
-// half-wave writing whole consecutive rows, then touch every bank once.
+// Position, within row r of a row-major LDS tile whose rows are ROW_BYTES long (at most
+// 256), of the row's 16-byte chunk `chunk`.  Chunks are XOR-permuted by the row's position
+// among the 256-byte bank spans: a quarter-wave reading one chunk of 16 consecutive rows, and
+// lanes writing whole consecutive rows, then touch every bank once.
+template <int ROW_BYTES>
+__device__ __forceinline__ int chunk_swizzle(int r, int chunk) {
+  constexpr int kChunks = ROW_BYTES / 16, kRowsPerSpan = 256 / ROW_BYTES;
+  return chunk ^ ((r / kRowsPerSpan) & (kChunks - 1));
+}
+// element offsets of a chunk: BF16 rows of BK elements (8 per chunk), FP32 rows (4 per chunk)
 template <int BK>
 __device__ __forceinline__ int bf16_chunk_swizzle(int r, int chunk) {
-  constexpr int kChunks = BK / 8, kRowsPerSpan = 128 / BK;
-  return (chunk ^ ((r / kRowsPerSpan) & (kChunks - 1))) * 8;
+  return chunk_swizzle<BK * 2>(r, chunk) * 8;
+}
+template <int BK>
+__device__ __forceinline__ int f32_chunk_swizzle(int r, int chunk) {
+  return chunk_swizzle<BK * 4>(r, chunk) * 4;
 }
 
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool AK = false>
 __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&acc)[TM][TN]) {
   constexpr int BM = WGM * TM * 32, BN = WGN * TN * 32;
-  using S = TileSmem<PREC, BM, BN, BK>;
+  using S = TileSmem<PREC, BM, BN, BK, AK>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   if constexpr (PREC == kFP32) {
+    // Per group of 8 k: lanes 0-31 hold k = kk..kk+3 of their row, lanes 32-63 k = kk+4..kk+7
+    // (one 16-byte chunk); MFMA m (2 k values: one per half-wave) takes component m.  A and
+    // B use the same assignment, so the 4 MFMAs sum over the 8 k values.
     const float* sA = reinterpret_cast<const float*>(smem);
-    const float* sB = sA + BK * S::LDF_A;
+    const float* sB = sA + S::kAFloats;
+    const int half = lane >> 5;
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      float a[TM], b[TN];
+    for (int kk = 0; kk < BK; kk += 8) {
+      f32x4 a[TM], b[TN];
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
-        a[tm] = sA[(kk + (lane >> 5)) * S::LDF_A + wm * TM * 32 + tm * 32 + (lane & 31)];
+      for (int tm = 0; tm < TM; ++tm) {
+        const int r = wm * TM * 32 + tm * 32 + (lane & 31);
+        if constexpr (AK) {
+          const float* col = sA + (kk + 4 * half) * S::LDF_A + r;
+          a[tm] = f32x4{col[0], col[S::LDF_A], col[2 * S::LDF_A], col[3 * S::LDF_A]};
+        } else {
+          a[tm] = *reinterpret_cast<const f32x4*>(sA + r * BK +
+                                                 f32_chunk_swizzle<BK>(r, kk / 4 + half));
+        }
+      }
 #pragma unroll
-      for (int tn = 0; tn < TN; ++tn)
-        b[tn] = sB[(kk + (lane >> 5)) * S::LDF_B + wn * TN * 32 + tn * 32 + (lane & 31)];
+      for (int tn = 0; tn < TN; ++tn) {
+        const int r = wn * TN * 32 + tn * 32 + (lane & 31);
+        b[tn] = *reinterpret_cast<const f32x4*>(sB + r * BK +
+                                               f32_chunk_swizzle<BK>(r, kk / 4 + half));
+      }
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int tn = 0; tn < TN; ++tn)
-          acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn)
+            acc[tm][tn] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(a[tm][m], b[tn][m], acc[tm][tn], 0, 0, 0);
     }
   } else {
     const uint16_t* sAh = reinterpret_cast<const uint16_t*>(smem);
@@ -261,10 +291,11 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
 // stages fit) the loop ping-pongs between two stages: one barrier per k-step, and the LDS
 // store of step k+1 overlaps the other waves' MFMAs on step k while the global loads of
 // step k+2 are in flight.  Otherwise one stage is refilled between two barriers.
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool PP, class Load, class Store>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, bool PP, bool AK, class Load,
+          class Store>
 __device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t kend, Load&& load,
                                             Store&& store, f32x16_t (&acc)[TM][TN]) {
-  constexpr int STAGE = TileSmem<PREC, WGM * TM * 32, WGN * TN * 32, BK>::kBytes;
+  constexpr int STAGE = TileSmem<PREC, WGM * TM * 32, WGN * TN * 32, BK, AK>::kBytes;
   if (kbeg >= kend) return;
   load(kbeg);
   if constexpr (PP) {
@@ -273,7 +304,7 @@ __device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t ke
     __syncthreads();
     int cur = 0;
     for (int64_t kb = kbeg; kb < kend; kb += BK) {
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem + cur * STAGE, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK, AK>(smem + cur * STAGE, acc);
       if (kb + BK < kend) {
         store(smem + (cur ^ 1) * STAGE);
         if (kb + 2 * BK < kend) load(kb + 2 * BK);
@@ -287,7 +318,7 @@ __device__ __forceinline__ void tile_k_loop(char* smem, int64_t kbeg, int64_t ke
       store(smem);
       __syncthreads();
       if (kb + BK < kend) load(kb + BK);
-      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK>(smem, acc);
+      mfma_block_compute<PREC, WGM, WGN, TM, TN, BK, AK>(smem, acc);
     }
   }
 }
@@ -343,16 +374,13 @@ struct F32KmajLoad {
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) v[it] = gload(reinterpret_cast<const f32x4*>(p + it * step));
   }
-  // FP32 smem, k-major [k][row]
-  __device__ __forceinline__ void store_kmajor(float* s, int lds) const {
+  // FP32 smem, row-major [row][k] with swizzled 16-byte chunks (the slot is one chunk)
+  __device__ __forceinline__ void store_rows(float* s) const {
     const int r = threadIdx.x / (BK / 4), c = threadIdx.x % (BK / 4);
 #pragma unroll
     for (int it = 0; it < kSlots; ++it) {
-      float* d = s + (c * 4) * lds + r + it * kRowStep;
-      d[0] = v[it].x;
-      d[lds] = v[it].y;
-      d[2 * lds] = v[it].z;
-      d[3 * lds] = v[it].w;
+      const int row = r + it * kRowStep;
+      *reinterpret_cast<f32x4*>(s + row * BK + f32_chunk_swizzle<BK>(row, c)) = v[it];
     }
   }
   // split to bf16 hi/lo, row-major [row][k]
@@ -445,7 +473,7 @@ struct Bf16KmajLoad {
 template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
-  using S = TileSmem<PREC, BM, BN, BK>;
+  using S = TileSmem<PREC, BM, BN, BK, false>;
   constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
@@ -475,7 +503,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
     F32KmajLoad<BN, NT, BK> lb;
     la.init(P.Z, P.ldz, m0);
     lb.init(P.Xf, P.ldz, n0);
-    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP, false>(
         smem, kbeg, kend,
         [&](int64_t kb) {
           la.load(kb);
@@ -483,8 +511,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
         },
         [&](char* st) {
           float* sA = reinterpret_cast<float*>(st);
-          la.store_kmajor(sA, S::LDF_A);
-          lb.store_kmajor(sA + BK * S::LDF_A, S::LDF_B);
+          la.store_rows(sA);
+          lb.store_rows(sA + S::kAFloats);
         },
         acc);
   } else {
@@ -493,7 +521,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
     Bf16KmajLoad<BN, NT, LO, BK> lb;
     la.init(P.Z, P.ldz, m0);
     lb.init(P.Xh, P.Xl, P.ldz, n0);
-    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP, false>(
         smem, kbeg, kend,
         [&](int64_t kb) {
           la.load(kb);
@@ -723,7 +751,7 @@ template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
-  using S = TileSmem<PREC, BE, BP, BK>;
+  using S = TileSmem<PREC, BE, BP, BK, true>;
   constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
@@ -749,7 +777,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
     F32KmajLoad<BP, NT, BK> lb;   // W particles x members, members contiguous
     la.init(P.Xf, P.ldz, e0);
     lb.init(P.W, P.ldn, i0);
-    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP, true>(
         smem, 0, P.ldn,
         [&](int64_t kb) {
           la.load(kb);
@@ -758,7 +786,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
         [&](char* st) {
           float* sA = reinterpret_cast<float*>(st);
           la.store(sA, S::LDF_A);
-          lb.store_kmajor(sA + BK * S::LDF_A, S::LDF_B);
+          lb.store_rows(sA + S::kAFloats);
         },
         acc);
   } else {
@@ -767,7 +795,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
     Bf16KmajLoad<BP, NT, LO, BK> lb;   // W particles x members
     la.init(P.XTh, P.XTl, P.ldn, e0);
     lb.init(P.Wh, P.Wl, P.ldn, i0);
-    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP>(
+    tile_k_loop<PREC, WGM, WGN, TM, TN, BK, PP, true>(
         smem, 0, P.ldn,
         [&](int64_t kb) {
           la.load(kb);
