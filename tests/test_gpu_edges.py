@@ -1,0 +1,68 @@
+"""Edge shapes of the analysis against the FP64 oracle: a single component, a single
+member (the prior score is then the Gaussian score of eq. 12 exactly), a single particle,
+a single pseudo-step, dimensions below one component quad, member counts at a tile
+boundary plus one, and a state of 2^22 + 3 components (particles sampled)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads
+from oracle import ensf as O
+from paper_2407_12168_amd import ensf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _run(dev, X, idx, y, sig, K, seed, M, precision, obs_op="arctan"):
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).to(dev)
+    post = torch.empty((M, X.shape[1]), device=dev)
+    ig = torch.from_numpy(idx).to(dev)
+    yg = torch.from_numpy(y).to(dev)
+    with ensf.Context(precision=precision, obs_op=obs_op) as ctx:
+        ensf.ensf_analysis(ctx.handle, Xg, post, ig, yg, sig, K, seed, 2)
+        st, nbad = ensf.ensf_sync_status(ctx.handle)
+    assert st == ensf.ENSF_OK, (st, nbad)
+    return post.cpu().numpy().astype(np.float64)
+
+
+# (members N, particles M_p, dimension d, pseudo-steps K, obs_op)
+SHAPES = [(1, 1, 1, 1, "arctan"), (1, 3, 5, 7, "arctan"), (2, 1, 3, 10, "linear"),
+          (3, 70, 4, 5, "arctan"), (65, 1, 129, 3, "linear"), (33, 33, 2, 12, "arctan")]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("N,M,d,K,op", SHAPES)
+def test_degenerate_shapes_match_oracle(dev, precision, N, M, d, K, op):
+    rng = np.random.default_rng(N * 1000 + d)
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    idx = np.arange(0, d, 2).astype(np.int32)
+    y = (np.arctan(rng.standard_normal(idx.size)) if op == "arctan"
+         else rng.standard_normal(idx.size)).astype(np.float32)
+    got = _run(dev, X, idx, y, 0.6, K, 31, M, precision, op)
+    want = O.analysis(X, idx, y, 0.6, K, 31, filter_id=2, obs_op=op, n_particles=M)
+    err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-30)
+    print(f"{precision} N={N} M={M} d={d} K={K} {op}: max rel diff {err:.2e}")
+    assert err <= 5e-4
+
+
+def test_large_dimension_sampled_particles(dev):
+    N, M, d, K = 8, 8, (1 << 22) + 3, 10
+    rng = np.random.default_rng(77)
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    idx = np.sort(rng.choice(d, d // 5, replace=False)).astype(np.int32)
+    y = np.arctan(rng.standard_normal(idx.size)).astype(np.float32)
+    rows = [0, M - 1]
+    want = O.analysis(X, idx, y, 0.5, K, 5, filter_id=2, particle_ids=rows, chunk=2)
+    for precision in ("fp32", "bf16x3"):
+        got = _run(dev, X, idx, y, 0.5, K, 5, M, precision)
+        err = O.rel_l2(got[rows], want)
+        print(f"d=2^22+3 {precision}: particles {rows} rel-L2 {err:.2e}")
+        assert err <= 1e-3
