@@ -367,6 +367,26 @@ void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) 
                          off, c->ws);
 }
 
+// Schedule of eq. 9 with alpha_t = 1 - t (1 - eps), beta_t^2 = t, damping h = 1 - t
+// (eq. 11), evaluated in FP64 and rounded once to FP32.
+StepScalars host_step_scalars(double t, double eps, int K) {
+  const double alpha = 1.0 - t * (1.0 - eps);
+  const double beta2 = t;
+  const double b = -(1.0 - eps) / alpha;
+  const double sigma2 = 1.0 - 2.0 * b * beta2;
+  const double dt = 1.0 / (double)(K > 0 ? K : 1);
+  StepScalars s;
+  s.alpha = (float)alpha;
+  s.inv_beta2 = (float)(1.0 / beta2);
+  s.b = (float)b;
+  s.sigma2 = (float)sigma2;
+  s.h = (float)(1.0 - t);
+  s.dt = (float)dt;
+  s.cnoise = (float)std::sqrt(sigma2 * dt);
+  s.damp = (float)(sigma2 * (1.0 - t) * dt);
+  return s;
+}
+
 struct Uploaded {
   GroupedLaunch rows;
   std::vector<GroupedLaunch> gram, wx;   // one per group
@@ -377,6 +397,7 @@ ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& 
   auto al = [](size_t v) { return (size_t)round_up((int64_t)v, 256); };
   size_t bytes = al(sizeof(ProbDev) * np) + al(sizeof(int32_t) * (np + 1));
   for (const Group& G : plan.groups) bytes += 2 * al(sizeof(int32_t) * (G.count + 1));
+  for (const ProbDev& P : plan.desc) bytes += al(sizeof(StepScalars) * (P.K + 1));
   ensf_status st = ensure_table(c, bytes);
   if (st != ENSF_OK) return st;
   if (c->tab_event_pending) HIP_TRY(hipEventSynchronize(c->tab_event));
@@ -387,6 +408,8 @@ ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& 
     off += al(n);
     return at;
   };
+  // descriptors first (their step-table pointers are filled in below), then prefix arrays,
+  // then one step table per problem
   const size_t o_desc = put(plan.desc.data(), sizeof(ProbDev) * np);
   const size_t o_rows = put(plan.pre_rows.data(), sizeof(int32_t) * (np + 1));
   std::vector<std::pair<size_t, size_t>> o_grp;
@@ -394,6 +417,17 @@ ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& 
     const size_t a = put(G.pre_gram.data(), sizeof(int32_t) * (G.count + 1));
     const size_t b = put(G.pre_wx.data(), sizeof(int32_t) * (G.count + 1));
     o_grp.emplace_back(a, b);
+  }
+  std::vector<StepScalars> table;
+  for (int f = 0; f < np; ++f) {
+    const ProbDev& P = plan.desc[f];
+    table.resize(P.K + 1);
+    for (int k = 0; k < P.K; ++k)
+      table[k] = host_step_scalars(1.0 - (double)k * (1.0 / (double)P.K), P.eps, P.K);
+    table[P.K] = host_step_scalars(P.t_score, P.eps, P.K);
+    const size_t o = put(table.data(), sizeof(StepScalars) * (P.K + 1));
+    reinterpret_cast<ProbDev*>(c->h_tab + o_desc)[f].steps =
+        reinterpret_cast<const StepScalars*>(c->d_tab + o);
   }
   HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, off, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(c->tab_event, s));

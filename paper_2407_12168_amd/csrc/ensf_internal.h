@@ -15,6 +15,13 @@ constexpr int kMaxMembers = 16384;
 
 // One analysis problem as the kernels see it (device-resident table, one entry per
 // problem of a batched call).
+// Per-step scalars in FP32, computed on the host in FP64 from (t, eps) exactly as the oracle
+// does and rounded once (a table per problem; the kernels read it with scalar loads).
+struct StepScalars {
+  float alpha, inv_beta2, b, sigma2, h, dt, cnoise;
+  float damp;   // sigma^2 h dt: weight of the likelihood score in the update
+};
+
 struct ProbDev {
   // caller-owned
   const float* X;           // N x d prior
@@ -45,15 +52,11 @@ struct ProbDev {
   int32_t obs_op;
   int32_t lik_implicit;     // 1: linearly implicit likelihood drift in the update
   double eps, t_score;
+  const StepScalars* steps;   // K + 1 entries: pseudo-steps 0..K-1, then the score time
   int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
   int32_t wx_tp, wx_te;       // W.X tiles along particles, state components
 };
 
-// Per-step scalars in FP32, computed in FP64 from (t, eps) exactly as the oracle does.
-struct StepScalars {
-  float alpha, inv_beta2, b, sigma2, h, dt, cnoise;
-  float damp;   // sigma^2 h dt: weight of the likelihood score in the update
-};
 
 // Prefix arrays of a grouped launch: tiles of problem f are [pre[f], pre[f+1]).
 struct GroupedLaunch {

@@ -20,6 +20,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ensf_internal.h"
 
 namespace ensf {
@@ -56,26 +58,6 @@ __device__ __forceinline__ double step_time(const ProbDev& P, int step) {
   return 1.0 - (double)step * dt;
 }
 
-// Schedule of eq. 9 with alpha_t = 1 - t (1 - eps), beta_t^2 = t, damping h = 1 - t
-// (eq. 11), evaluated in FP64 and rounded once to FP32.
-__device__ __forceinline__ StepScalars step_scalars(double t, double eps, int K) {
-  const double alpha = 1.0 - t * (1.0 - eps);
-  const double beta2 = t;
-  const double b = -(1.0 - eps) / alpha;
-  const double sigma2 = 1.0 - 2.0 * b * beta2;
-  const double dt = 1.0 / (double)(K > 0 ? K : 1);
-  StepScalars s;
-  s.alpha = (float)alpha;
-  s.inv_beta2 = (float)(1.0 / beta2);
-  s.b = (float)b;
-  s.sigma2 = (float)sigma2;
-  s.h = (float)(1.0 - t);
-  s.dt = (float)dt;
-  s.cnoise = (float)sqrt(sigma2 * dt);
-  s.damp = (float)(sigma2 * (1.0 - t) * dt);
-  return s;
-}
-
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies with the
 // Weyl key schedule.
 struct Words4 { uint32_t w0, w1, w2, w3; };
@@ -88,7 +70,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
     const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
     const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96: odd number of set inputs)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -136,11 +120,12 @@ __device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
 // a_e = sum y / sigma_o^2 and b_e = count / sigma_o^2 of the component (eq. 5).
 // The fused multiply-adds of the score and the update are written out and the compiler may
 // fuse nothing else, so every kernel that inlines them computes the same bits.
+template <int OP>
 __device__ __forceinline__ float posterior_score(float z, float xh, float a_e, float b_e,
-                                                 const StepScalars& sc, int op) {
+                                                 const StepScalars& sc) {
 #pragma clang fp contract(off)
   const float prior = fmaf(sc.alpha, xh, -z) * sc.inv_beta2;
-  const float lik = (op == kArctan)
+  const float lik = (OP == kArctan)
                         ? fmaf(-b_e, atanf(z), a_e) * __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f))
                         : fmaf(-b_e, z, a_e);
   return fmaf(sc.h, lik, prior);
@@ -152,14 +137,15 @@ __device__ __forceinline__ float posterior_score(float z, float xh, float a_e, f
 // Linearly implicit likelihood: the L term is divided by 1 + sigma^2 h dt kappa with the
 // Gauss-Newton curvature kappa = B g'(z)^2, which keeps the step stable when dt is not
 // small against sigma_o^2; without observations (B = 0) both are the same step.
+template <int OP, bool IMPLICIT>
 __device__ __forceinline__ float update_step(float z, float xh, float a_e, float b_e, float xi,
-                                             const StepScalars& sc, int op, bool implicit) {
+                                             const StepScalars& sc) {
 #pragma clang fp contract(off)
   const float prior = fmaf(sc.alpha, xh, -z) * sc.inv_beta2;
-  const float gp = (op == kArctan) ? __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f)) : 1.0f;
-  const float lik = (op == kArctan) ? fmaf(-b_e, atanf(z), a_e) * gp : fmaf(-b_e, z, a_e);
+  const float gp = (OP == kArctan) ? __builtin_amdgcn_rcpf(fmaf(z, z, 1.0f)) : 1.0f;
+  const float lik = (OP == kArctan) ? fmaf(-b_e, atanf(z), a_e) * gp : fmaf(-b_e, z, a_e);
   float w = sc.damp;
-  if (implicit) w *= __builtin_amdgcn_rcpf(fmaf((sc.damp * b_e) * gp, gp, 1.0f));
+  if constexpr (IMPLICIT) w *= __builtin_amdgcn_rcpf(fmaf((sc.damp * b_e) * gp, gp, 1.0f));
   const float drift = fmaf(sc.b, z, -(sc.sigma2 * prior));   // b z - sigma^2 prior
   float out = fmaf(-drift, sc.dt, z);
   out = fmaf(w, lik, out);
@@ -690,7 +676,7 @@ __device__ __forceinline__ WxEpi make_wx_epi(const ProbDev& P, int step, int64_t
   E.Mp = P.Mp;
   E.i0 = i0;
   E.e0 = e0;
-  E.sc = step_scalars(step_time(P, step), P.eps, P.K);
+  E.sc = P.steps[step < 0 ? P.K : step];
   E.obs_op = P.obs_op;
   E.step = step;
   E.implicit = P.lik_implicit != 0;
@@ -704,7 +690,7 @@ __device__ __forceinline__ WxEpi make_wx_epi(const ProbDev& P, int step, int64_t
 // One accumulator quad of a lane: block (a, b), register group gq, i.e. xhat for four
 // consecutive components e..e+3 of particle i (one Philox counter).  SCORE writes the
 // posterior score; otherwise the particle components are advanced one step in place.
-template <int WGN, int TM, int TN, bool SCORE>
+template <int WGN, int TM, int TN, bool SCORE, int OP, bool IMPLICIT>
 __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc)[TM][TN], int a,
                                             int b, int gq, unsigned int& bad) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -721,10 +707,10 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
   const int64_t rem = E.d - e;
   if constexpr (SCORE) {
     float* so = E.score_out + i * E.d + e;
-    so[0] = posterior_score(z.x, xh0, av.x, bv.x, E.sc, E.obs_op);
-    if (rem > 1) so[1] = posterior_score(z.y, xh1, av.y, bv.y, E.sc, E.obs_op);
-    if (rem > 2) so[2] = posterior_score(z.z, xh2, av.z, bv.z, E.sc, E.obs_op);
-    if (rem > 3) so[3] = posterior_score(z.w, xh3, av.w, bv.w, E.sc, E.obs_op);
+    so[0] = posterior_score<OP>(z.x, xh0, av.x, bv.x, E.sc);
+    if (rem > 1) so[1] = posterior_score<OP>(z.y, xh1, av.y, bv.y, E.sc);
+    if (rem > 2) so[2] = posterior_score<OP>(z.z, xh2, av.z, bv.z, E.sc);
+    if (rem > 3) so[3] = posterior_score<OP>(z.w, xh3, av.w, bv.w, E.sc);
   } else {
     const Words4 w =
         philox4x32_10((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)E.step, E.filt, E.k0, E.k1);
@@ -732,10 +718,10 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
     box_muller(w.w0, w.w1, n0, n1);
     box_muller(w.w2, w.w3, n2, n3);
     f32x4 zn;
-    zn.x = update_step(z.x, xh0, av.x, bv.x, n0, E.sc, E.obs_op, E.implicit);
-    zn.y = update_step(z.y, xh1, av.y, bv.y, n1, E.sc, E.obs_op, E.implicit);
-    zn.z = update_step(z.z, xh2, av.z, bv.z, n2, E.sc, E.obs_op, E.implicit);
-    zn.w = update_step(z.w, xh3, av.w, bv.w, n3, E.sc, E.obs_op, E.implicit);
+    zn.x = update_step<OP, IMPLICIT>(z.x, xh0, av.x, bv.x, n0, E.sc);
+    zn.y = update_step<OP, IMPLICIT>(z.y, xh1, av.y, bv.y, n1, E.sc);
+    zn.z = update_step<OP, IMPLICIT>(z.z, xh2, av.z, bv.z, n2, E.sc);
+    zn.w = update_step<OP, IMPLICIT>(z.w, xh3, av.w, bv.w, n3, E.sc);
     if (rem < 4) {  // ragged tail: keep the padding at zero
       zn.w = 0.0f;
       if (rem < 3) zn.z = 0.0f;
@@ -813,12 +799,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 
   const WxEpi E = make_wx_epi(P, step, i0, e0, true);
   unsigned int bad = 0;
+  // one specialised epilogue per observation operator and time-stepping variant (uniform)
+  auto epilogue = [&](auto op_tag, auto impl_tag) {
+    constexpr int OP = decltype(op_tag)::value;
+    constexpr bool IMPL = decltype(impl_tag)::value;
 #pragma unroll
-  for (int b = 0; b < TN; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
-    for (int a = 0; a < TM; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int gq = 0; gq < 4; ++gq) wx_epi_quad<WGN, TM, TN, SCORE>(E, acc, a, b, gq, bad);
+        for (int gq = 0; gq < 4; ++gq)
+          wx_epi_quad<WGN, TM, TN, SCORE, OP, IMPL>(E, acc, a, b, gq, bad);
+  };
+  using ArcT = std::integral_constant<int, kArctan>;
+  using LinT = std::integral_constant<int, kLinear>;
+  using Yes = std::true_type;
+  using No = std::false_type;
+  if (E.obs_op == kArctan) {
+    if (E.implicit && !SCORE) epilogue(ArcT{}, Yes{}); else epilogue(ArcT{}, No{});
+  } else {
+    if (E.implicit && !SCORE) epilogue(LinT{}, Yes{}); else epilogue(LinT{}, No{});
+  }
   if (!SCORE && bad) atomicAdd(nonfinite, (unsigned long long)bad);
 }
 
