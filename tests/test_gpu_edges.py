@@ -66,3 +66,18 @@ def test_large_dimension_sampled_particles(dev):
         err = O.rel_l2(got[rows], want)
         print(f"d=2^22+3 {precision}: particles {rows} rel-L2 {err:.2e}")
         assert err <= 1e-3
+
+
+@pytest.mark.parametrize("N,d", [(32, 16384), (33, 4096), (32, 16385), (17, 4097)])
+def test_member_and_dimension_boundaries(dev, N, d):
+    # member counts at and one past a 32-row tile, dimensions at and one past a power of two
+    rng = np.random.default_rng(N + d)
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    idx = np.sort(rng.choice(d, d // 3, replace=False)).astype(np.int32)
+    y = np.arctan(rng.standard_normal(idx.size)).astype(np.float32)
+    M, K = 6, 40
+    got = _run(dev, X, idx, y, 0.5, K, 9, M, "fp32")
+    want = O.analysis(X, idx, y, 0.5, K, 9, filter_id=2, n_particles=M)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"N={N} d={d}: max rel diff {err:.2e}")
+    assert err <= 5e-4
