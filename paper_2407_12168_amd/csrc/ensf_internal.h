@@ -79,7 +79,8 @@ enum WxCfg : int {
   kWx128 = 0, kWx64 = 1, kWx32 = 2, kWx256 = 3, kWx128x256 = 4,
   kWx256w = 5,        // 256 x 128 on 4 waves of 128 x 64
   kWx128x256w = 6,    // 128 x 256 on 4 waves of 64 x 128
-  kNumWx = 7
+  kWx128e = 7,        // 128 x 128 on 8 waves of 64 x 32 (fewer registers per wave)
+  kNumWx = 8
 };
 
 // kGram256 is 256 particles x 128 members; kWx256 is 256 components x 128 particles.
@@ -94,8 +95,8 @@ inline int gram_bn(int c) {
 }
 inline int wx_be(int c) { return c == kWx256 || c == kWx256w ? 256 : 128; }
 inline int wx_bp(int c) {
-  return c == kWx128x256 || c == kWx128x256w     ? 256
-         : c == kWx128 || c == kWx256 || c == kWx256w ? 128
+  return c == kWx128x256 || c == kWx128x256w                     ? 256
+         : c == kWx128 || c == kWx256 || c == kWx256w || c == kWx128e ? 128
          : c == kWx64                              ? 64
                                                    : 32;
 }

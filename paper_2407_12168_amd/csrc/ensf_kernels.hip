@@ -1029,7 +1029,7 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
   }
 
 // (components x particles) per config: 128x128, 128x64, 128x32, 256x128, 128x256, then
-// 256x128 and 128x256 on four waves with larger per-wave tiles
+// 256x128 and 128x256 on four waves with larger per-wave tiles, 128x128 on eight waves
 #define ENSF_WX_ALL(PR)                     \
   ENSF_WX_CASE(PR, kWx128, 2, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx64, 2, 2, 2, 1)       \
@@ -1037,7 +1037,8 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
   ENSF_WX_CASE(PR, kWx256, 4, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)  \
   ENSF_WX_CASE(PR, kWx256w, 2, 2, 4, 2)     \
-  ENSF_WX_CASE(PR, kWx128x256w, 2, 2, 2, 4)
+  ENSF_WX_CASE(PR, kWx128x256w, 2, 2, 2, 4) \
+  ENSF_WX_CASE(PR, kWx128e, 2, 4, 2, 1)
 
 hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
                      int step, unsigned long long* nonfinite, hipStream_t s) {
