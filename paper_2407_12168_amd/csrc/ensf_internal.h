@@ -72,7 +72,8 @@ enum GramCfg : int {
   kGram128 = 0, kGram64 = 1, kGram32 = 2, kGram256 = 3,
   kGram256x256 = 4,   // 4 waves of 128 x 128
   kGram256w = 5,      // 256 x 128 on 4 waves of 128 x 64
-  kNumGram = 6
+  kGram128e = 6,      // 128 x 128 on 8 waves of 64 x 32
+  kNumGram = 7
 };
 // W.X tiles: state components x particles.
 enum WxCfg : int {
@@ -80,13 +81,14 @@ enum WxCfg : int {
   kWx256w = 5,        // 256 x 128 on 4 waves of 128 x 64
   kWx128x256w = 6,    // 128 x 256 on 4 waves of 64 x 128
   kWx128e = 7,        // 128 x 128 on 8 waves of 64 x 32 (fewer registers per wave)
-  kNumWx = 8
+  kWx128f = 8,        // 128 x 128 on 8 waves of 32 x 64
+  kNumWx = 9
 };
 
 // kGram256 is 256 particles x 128 members; kWx256 is 256 components x 128 particles.
 inline int gram_bm(int c) {
   return c == kGram256 || c == kGram256x256 || c == kGram256w ? 256
-         : c == kGram128                                    ? 128
+         : c == kGram128 || c == kGram128e                  ? 128
          : c == kGram64                                     ? 64
                                                             : 32;
 }
@@ -96,7 +98,7 @@ inline int gram_bn(int c) {
 inline int wx_be(int c) { return c == kWx256 || c == kWx256w ? 256 : 128; }
 inline int wx_bp(int c) {
   return c == kWx128x256 || c == kWx128x256w                     ? 256
-         : c == kWx128 || c == kWx256 || c == kWx256w || c == kWx128e ? 128
+         : c == kWx128 || c == kWx256 || c == kWx256w || c == kWx128e || c == kWx128f ? 128
          : c == kWx64                              ? 64
                                                    : 32;
 }

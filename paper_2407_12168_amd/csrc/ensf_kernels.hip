@@ -999,7 +999,8 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
   ENSF_GRAM_CASE(PR, kGram32, 1, 1, 1, 1)  \
   ENSF_GRAM_CASE(PR, kGram256, 4, 2, 2, 2)    \
   ENSF_GRAM_CASE32(PR, kGram256x256, 2, 2, 4, 4) \
-  ENSF_GRAM_CASE(PR, kGram256w, 2, 2, 4, 2)
+  ENSF_GRAM_CASE(PR, kGram256w, 2, 2, 4, 2)    \
+  ENSF_GRAM_CASE(PR, kGram128e, 2, 4, 2, 1)
 
 hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g, int step,
                        hipStream_t s) {
@@ -1029,7 +1030,8 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
   }
 
 // (components x particles) per config: 128x128, 128x64, 128x32, 256x128, 128x256, then
-// 256x128 and 128x256 on four waves with larger per-wave tiles, 128x128 on eight waves
+// 256x128 and 128x256 on four waves with larger per-wave tiles, 128x128 on eight waves (two
+// wave shapes)
 #define ENSF_WX_ALL(PR)                     \
   ENSF_WX_CASE(PR, kWx128, 2, 2, 2, 2)      \
   ENSF_WX_CASE(PR, kWx64, 2, 2, 2, 1)       \
@@ -1038,7 +1040,8 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
   ENSF_WX_CASE(PR, kWx128x256, 2, 4, 2, 2)  \
   ENSF_WX_CASE(PR, kWx256w, 2, 2, 4, 2)     \
   ENSF_WX_CASE(PR, kWx128x256w, 2, 2, 2, 4) \
-  ENSF_WX_CASE(PR, kWx128e, 2, 4, 2, 1)
+  ENSF_WX_CASE(PR, kWx128e, 2, 4, 2, 1)     \
+  ENSF_WX_CASE(PR, kWx128f, 4, 2, 1, 2)
 
 hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
                      int step, unsigned long long* nonfinite, hipStream_t s) {

@@ -14,7 +14,7 @@ from paper_2407_12168_amd import ensf
 pytestmark = pytest.mark.gpu
 
 N, M, D, K, SIG = 70, 130, 3001, 20, 0.5
-N_GRAM, N_WX = 6, 8
+N_GRAM, N_WX = 7, 9
 PREC_ID = {"fp32": 0, "bf16x3": 1}
 
 
