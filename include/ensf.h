@@ -17,7 +17,9 @@
  *   b = d log(alpha_t)/dt, sigma^2 = d(beta_t^2)/dt - 2 b beta_t^2 (eq. 9), h(t) = 1 - t,
  *   and the Gaussian likelihood of eqs. 2 and 5 with R = obs_sigma^2 I,
  *       log p(y | z) = -sum_m (y_m - g(z[idx_m]))^2 / (2 obs_sigma^2),
- *   g = arctan (ENSF_OBS_ARCTAN) or the identity (ENSF_OBS_LINEAR).
+ *   g = arctan (ENSF_OBS_ARCTAN) or the identity (ENSF_OBS_LINEAR).  With
+ *   ensf_options.lik_step = ENSF_LIK_IMPLICIT the likelihood part of the drift is
+ *   advanced linearly implicitly instead (see ensf_lik_step).
  *
  * The noise xi and the initial particles come from Philox4x32-10 (key = seed,
  * counter = (element / 4, particle, step, filter_id), step = 0xFFFFFFFF for the

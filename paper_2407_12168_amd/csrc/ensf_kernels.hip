@@ -112,10 +112,6 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
   lo = bf16_bits((__bf16)(x - (float)h));
 }
 
-__device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) {
-  return (uint32_t)a | ((uint32_t)b << 16);
-}
-
 // Damped posterior score (eq. 17) of one component given xhat = sum_j w_j x_j.
 // a_e = sum y / sigma_o^2 and b_e = count / sigma_o^2 of the component (eq. 5).
 // The fused multiply-adds of the score and the update are written out and the compiler may

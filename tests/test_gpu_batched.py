@@ -116,3 +116,40 @@ def test_batched_autotune_then_match_oracle(dev, precision, tmp_path):
         want = O.analysis(p["X"], p["idx"], p["y"], p["sig"], p["K"], p["seed"], p["fid"],
                           n_particles=p["M"])
         assert np.abs(g - want).max() <= 5e-4 * np.abs(want).max()
+
+
+def test_two_contexts_on_two_streams_concurrently(dev):
+    # contexts are independent: two analyses enqueued on two streams at once give the same
+    # bits as the same analyses run one after the other
+    probs = _problems(4000)[:2]
+    ins = []
+    for p in probs:
+        X = torch.from_numpy(p["X"]).to(dev)
+        idx = torch.from_numpy(p["idx"]).to(dev)
+        y = torch.from_numpy(p["y"]).to(dev)
+        ins.append((X, idx, y, p))
+    seq = []
+    for X, idx, y, p in ins:
+        post = torch.empty((p["M"], X.shape[1]), device=dev)
+        with ensf.Context(precision="fp32") as ctx:
+            ensf.ensf_analysis(ctx.handle, X, post, idx, y, p["sig"], p["K"], p["seed"], p["fid"])
+            assert ensf.ensf_sync_status(ctx.handle)[0] == ensf.ENSF_OK
+        seq.append(post.cpu().numpy())
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    ctxs = [ensf.Context(precision="fp32"), ensf.Context(precision="fp32")]
+    outs = []
+    try:
+        for (X, idx, y, p), s, c in zip(ins, streams, ctxs):
+            post = torch.empty((p["M"], X.shape[1]), device=dev)
+            ensf.ensf_analysis(c.handle, X, post, idx, y, p["sig"], p["K"], p["seed"], p["fid"],
+                               stream=s)
+            outs.append(post)
+        for c in ctxs:
+            assert ensf.ensf_sync_status(c.handle)[0] == ensf.ENSF_OK
+    finally:
+        for c in ctxs:
+            c.destroy()
+    for a, b in zip(seq, outs):
+        np.testing.assert_array_equal(a, b.cpu().numpy())
