@@ -27,7 +27,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # calibrated with a plain copy of known size (profiles/hbm_traffic_d32768_n256_fp32.md);
 # keyed by (workload config, precision, kernel).  Absent entries are reported as null.
-MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 105.6e6}
+MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 105.65e6}
 WORKLOAD = {
     1: "EnSF analysis d=2x64x64=8192, N=M_p=20, arctan obs of all components, sigma_o=0.05, K=100",
     2: "EnSF analysis d=2x128x128=32768, N=M_p=256, arctan obs of a random 25% subset, "
@@ -98,7 +98,7 @@ def run_cycle_bench(a):
     print(json.dumps(line), flush=True)
 
 
-def run_form(probs, precision, steps, warmup, dev, lik_step="explicit"):
+def run_form(probs, precision, steps, warmup, dev, lik_step="explicit", wx_sparse=False):
     """Times ensf_analysis (one problem) or ensf_analysis_batched (several) on `probs`."""
     import torch
     from paper_2407_12168_amd import ensf
@@ -113,7 +113,8 @@ def run_form(probs, precision, steps, warmup, dev, lik_step="explicit"):
         tens.append((X, post, idx, val))
         descs.append(ensf.make_problem(X, post, idx, val, p.sigma_o, p.n_steps, p.seed,
                                        p.filter_id))
-    ctx = ensf.Context(precision=precision, use_graph=True, lik_step=lik_step)
+    ctx = ensf.Context(precision=precision, use_graph=True, lik_step=lik_step,
+                       wx_sparse=wx_sparse)
     h = ctx.handle
 
     def one():
@@ -147,11 +148,13 @@ def run_form(probs, precision, steps, warmup, dev, lik_step="explicit"):
     return ms, [m / n_launch for m in phase_ms]
 
 
-def roofline(probs, precision, phase_avg_ms, config=None):
-    # algorithmic flops per launch: Gram = sum 2*M_p*N*d, W.X the same (split forms issue 3x)
+def roofline(probs, precision, phase_avg_ms, config=None, wx_sparse=False):
+    # algorithmic flops per launch: Gram = sum 2*M_p*N*d, W.X the same (split forms issue 3x).
+    # With the degenerate-weight W.X most of its tiles are gathers, not contractions, so the
+    # Gram is the kernel priced against the MFMA peak.
     flops = sum(2.0 * p.n_members * p.n_members * p.dim for p in probs)
     names = ("k_gram", "k_softmax", "k_wx")
-    dom = 0 if phase_avg_ms[0] >= phase_avg_ms[2] else 2
+    dom = 0 if wx_sparse or phase_avg_ms[0] >= phase_avg_ms[2] else 2
     achieved = flops / (phase_avg_ms[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
     traffic = MEASURED_TRAFFIC.get((config, precision, names[dom]))
@@ -201,6 +204,10 @@ def main():
                          "fp32/bf16x3; 'none' to skip)")
     ap.add_argument("--lik-step", default="explicit", choices=("explicit", "implicit"),
                     help="time stepping of the likelihood drift (implicit: stable at any K)")
+    ap.add_argument("--wx-sparse", action="store_true",
+                    help="degenerate-weight W.X variant (reported apart from the dense path)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the degenerate-weight W.X variant reported beside the dense path")
     ap.add_argument("--cpu-particles", type=int, default=80,
                     help="particles of the oracle's timed sample (about 10 s at the default "
                          "workload)")
@@ -224,17 +231,38 @@ def main():
     else:
         probs = [workloads.config_problem(a.config)]
     print(f"# workload: {WORKLOAD[a.config]}", file=sys.stderr, flush=True)
-    ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev, a.lik_step)
+    ms, phase = run_form(probs, a.precision, a.steps, a.warmup, dev, a.lik_step, a.wx_sparse)
     print(f"# {a.precision}: {ms:.3f} ms per analysis", file=sys.stderr, flush=True)
     other = a.other_form or ("bf16x3" if a.precision == "fp32" else "fp32")
     if other != "none":
-        ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev, a.lik_step)
+        ms2, phase2 = run_form(probs, other, max(2, a.steps // 2), 1, dev, a.lik_step,
+                               a.wx_sparse)
         print(f"# {other}: {ms2:.3f} ms per analysis", file=sys.stderr, flush=True)
+    variant = None
+    if not a.wx_sparse and not a.no_variants:
+        ms3, phase3 = run_form(probs, a.precision, max(2, a.steps // 2), 1, dev, a.lik_step,
+                               True)
+        print(f"# {a.precision} degenerate-weight W.X: {ms3:.3f} ms per analysis",
+              file=sys.stderr, flush=True)
+        # the gather tiles are bound by HBM, not by the matrix cores: priced on the bytes every
+        # W.X launch must move (Z read and written, the weights: 2*M_p*d*4 + M_p*N*4); the X
+        # rows the gathers read depend on the weights and are left out
+        wx_bytes = sum(4.0 * (2 * p.n_members * p.dim + p.n_members ** 2) for p in probs)
+        gbs = wx_bytes / (phase3[2] * 1e-3) / 1e9
+        variant = {"value": None, "ms_per_step": ms3,
+                   "k_wx_hbm": {"achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                                "frac": round(gbs / 8000.0, 4)},
+                   "phase_avg_ms": {k: round(v, 5) for k, v in
+                                    zip(("k_gram", "k_softmax", "k_wx"), phase3)},
+                   "note": "same analysis; W.X tiles whose weight rows have at most 8 weights "
+                           ">= 2^-30 gather xhat from those members (dense tiles otherwise)"}
     ndk = sum(p.n_members * p.dim * p.n_steps for p in probs)
     p0 = probs[0]
     cfg = {"workload": WORKLOAD[a.config], "precision": a.precision}
     if a.lik_step != "explicit":
         cfg["lik_step"] = a.lik_step
+    if a.wx_sparse:
+        cfg["wx"] = "degenerate-weight variant (sparse W.X where rows allow)"
     if len(probs) == 1:
         cfg.update(members=p0.n_members, particles=p0.n_members, dim=p0.dim,
                    pseudo_steps=p0.n_steps, obs=int(p0.obs_idx.size))
@@ -250,13 +278,17 @@ def main():
         "dtype": "f32" if a.precision == "fp32" else a.precision,
         "data": "synthetic",
         "config": cfg,
-        "roofline": roofline(probs, a.precision, phase, a.config),
+        "roofline": roofline(probs, a.precision, phase, a.config, a.wx_sparse),
     }
     if other != "none":
         line["forms"] = {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
-                                 "roofline": roofline(probs, other, phase2, a.config)},
+                                 "roofline": roofline(probs, other, phase2, a.config,
+                                                      a.wx_sparse)},
                          "speedup_bf16x3_over_fp32":
                              (ms / ms2) if a.precision == "fp32" else (ms2 / ms)}
+    if variant is not None:
+        variant["value"] = ndk / (variant["ms_per_step"] * 1e-3)
+        line["variants"] = {"wx_sparse": variant}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(probs, a.cpu_particles, a.lik_step)
     print(json.dumps(line), flush=True)

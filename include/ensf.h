@@ -87,6 +87,12 @@ typedef struct {
   int32_t device;         /* HIP device ordinal the context lives on */
   const char* tune_cache; /* JSON tile-table path for the autotuner; NULL = $ENSF_TUNE_CACHE */
   int32_t lik_step;       /* ensf_lik_step; default EXPLICIT */
+  int32_t wx_sparse;      /* 1: degenerate-weight W.X (variant, default 0): per pseudo-step,
+                             W.X tiles whose particles all have at most 8 weights >= 2^-30
+                             compute xhat (eq. 15, weights of eq. 16) = sum of those
+                             weights times their members (FP32) instead of the dense product;
+                             the weights below 2^-30 are dropped (error below
+                             n_members * 2^-30 * max |x|); others run dense */
 } ensf_options;
 
 /* One analysis problem of a batched call; fields as in ensf_analysis. */
@@ -106,7 +112,7 @@ typedef struct {
 } ensf_problem;
 
 /* Fills *opt with the defaults (FP32, arctan, eps 0.05, no relaxation, graphs on, device 0,
-   explicit step). */
+   explicit step, dense W.X). */
 void ensf_default_options(ensf_options* opt);
 
 /* Creates a context on opt->device (NULL opt = defaults).  *out receives the handle.

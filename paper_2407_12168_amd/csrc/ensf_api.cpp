@@ -178,8 +178,7 @@ TileChoice heuristic_tiles(int64_t n, int64_t mp) {
 
 // Lays out one problem's workspace at offset `off` (bytes) and fills its descriptor.
 size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileChoice& tc,
-                      int obs_op, int lik_step, double eps, double wg_target, size_t off,
-                      char* base) {
+                      const ensf_options& opt, double wg_target, size_t off, char* base) {
   auto take = [&](size_t bytes) {
     off = round_up(off, kAlign);
     char* ptr = base ? base + off : nullptr;
@@ -200,9 +199,10 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.seed_hi = (uint32_t)(p.seed >> 32);
   P.filter = p.filter_id;
   P.inv_sig2 = p.n_obs > 0 ? (float)(1.0 / ((double)p.obs_sigma * (double)p.obs_sigma)) : 0.0f;
-  P.obs_op = obs_op;
-  P.lik_implicit = lik_step == ENSF_LIK_IMPLICIT ? 1 : 0;
-  P.eps = eps;
+  P.obs_op = opt.obs_op;
+  P.lik_implicit = opt.lik_step == ENSF_LIK_IMPLICIT ? 1 : 0;
+  P.sparse = opt.wx_sparse ? 1 : 0;
+  P.eps = opt.eps_alpha;
   P.t_score = 1.0;
   const int bm = gram_bm(tc.gram), bn = gram_bn(tc.gram);
   P.Mp_pad = (int32_t)round_up(P.Mp, std::max({bm, wx_bp(tc.wx), 64}));
@@ -244,6 +244,9 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
     P.Wh = reinterpret_cast<uint16_t*>(take((size_t)P.Mp_pad * P.ldn * 2));
     P.Wl = reinterpret_cast<uint16_t*>(take((size_t)P.Mp_pad * P.ldn * 2));
   }
+  P.sp_cnt = reinterpret_cast<int32_t*>(take((size_t)P.Mp_pad * 4));
+  P.sp_idx = reinterpret_cast<int32_t*>(take((size_t)P.Mp_pad * kSparseMax * 4));
+  P.sp_w = reinterpret_cast<float*>(take((size_t)P.Mp_pad * kSparseMax * 4));
   return round_up(off, kAlign);
 }
 
@@ -339,8 +342,7 @@ ensf_status build_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan
     plan.wg_target[i] =
         std::max(8.0, 1024.0 * (double)p.n_members * p.n_particles * p.dim / total);
     ProbDev& P = plan.desc[i];
-    off = layout_problem(P, p, prec, plan.tc[i], c->opt.obs_op, c->opt.lik_step,
-                         c->opt.eps_alpha, plan.wg_target[i], off, nullptr);
+    off = layout_problem(P, p, prec, plan.tc[i], c->opt, plan.wg_target[i], off, nullptr);
     Group& G = plan.groups[gid[f]];
     const int j = i - G.first;
     const int64_t gw = (int64_t)P.gram_tm * P.gram_tn * P.S;
@@ -363,8 +365,7 @@ void bind_plan(ensf_ctx* c, const std::vector<ensf_problem>& probs, Plan& plan) 
   size_t off = 0;
   for (size_t i = 0; i < plan.desc.size(); ++i)
     off = layout_problem(plan.desc[i], probs[plan.order[i]], c->opt.precision, plan.tc[i],
-                         c->opt.obs_op, c->opt.lik_step, c->opt.eps_alpha, plan.wg_target[i],
-                         off, c->ws);
+                         c->opt, plan.wg_target[i], off, c->ws);
 }
 
 // Schedule of eq. 9 with alpha_t = 1 - t (1 - eps), beta_t^2 = t, damping h = 1 - t
@@ -463,6 +464,7 @@ ensf_status zero_problem(const ProbDev& P, int prec, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(P.xnorm, 0, (size_t)P.ldn * 4, s));
   HIP_TRY(hipMemsetAsync(P.A, 0, (size_t)P.ldz * 4, s));
   HIP_TRY(hipMemsetAsync(P.B, 0, (size_t)P.ldz * 4, s));
+  HIP_TRY(hipMemsetAsync(P.sp_cnt, 0, (size_t)P.Mp_pad * 4, s));
   return ENSF_OK;
 }
 
@@ -499,7 +501,8 @@ ensf_status launch_grams(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k
 ensf_status launch_wxs(ensf_ctx* c, const Plan& plan, const Uploaded& u, int k, hipStream_t s) {
   for (size_t g = 0; g < plan.groups.size(); ++g)
     HIP_TRY(launch_wx(c->opt.precision, plan.groups[g].tiles.wx, plan.groups[g].tiles.wx_bk,
-                      plan.groups[g].tiles.wx_st, false, u.wx[g], k, c->d_counters, s));
+                      plan.groups[g].tiles.wx_st, false, c->opt.wx_sparse != 0, u.wx[g], k,
+                      c->d_counters, s));
   return ENSF_OK;
 }
 
@@ -699,6 +702,7 @@ void ensf_default_options(ensf_options* opt) {
   opt->precision = ENSF_PREC_FP32;
   opt->obs_op = ENSF_OBS_ARCTAN;
   opt->lik_step = ENSF_LIK_EXPLICIT;
+  opt->wx_sparse = 0;
   opt->eps_alpha = 0.05;
   opt->spread_relax = 0.0;
   opt->use_graph = 1;
@@ -713,7 +717,7 @@ ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out) {
   ensf_default_options(&o);
   if (opt) o = *opt;
   if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1 || o.lik_step < 0 ||
-      o.lik_step > 1)
+      o.lik_step > 1 || o.wx_sparse < 0 || o.wx_sparse > 1)
     return ENSF_EINVAL;
   if (!(o.eps_alpha > 0.0 && o.eps_alpha < 1.0)) return ENSF_EINVAL;
   if (!(o.spread_relax >= 0.0 && o.spread_relax <= 1.0)) return ENSF_EINVAL;
@@ -794,7 +798,7 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   const TileChoice& tiles = plan.groups[0].tiles;
   HIP_TRY(launch_gram(prec, tiles.gram, tiles.gram_bk, tiles.gram_st, u.gram[0], -1, s));
   HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
-  HIP_TRY(launch_wx(prec, tiles.wx, 32, 2, true, u.wx[0], -1, ctx->d_counters, s));
+  HIP_TRY(launch_wx(prec, tiles.wx, 32, 2, true, false, u.wx[0], -1, ctx->d_counters, s));
   ctx->last_stream = s;
   ctx->has_last_stream = true;
   return ENSF_OK;

@@ -12,6 +12,11 @@ enum ObsOp : int { kArctan = 0, kLinear = 1 };
 // matrix are padded to multiples of the chosen tile shapes (at least 64 and 128), so
 // kernels never read outside an allocation; the padding is zero.
 constexpr int kMaxMembers = 16384;
+// Degenerate-weight W.X: a weight row counts as sparse when at most kSparseMax of its weights
+// reach kSparseTau (= 2^-30); the smaller ones (at most N of them, below FP32 resolution of a
+// unit-sum row) are dropped.
+constexpr int kSparseMax = 8;
+constexpr float kSparseTau = 9.313225746154785e-10f;
 
 // One analysis problem as the kernels see it (device-resident table, one entry per
 // problem of a batched call).
@@ -53,6 +58,10 @@ struct ProbDev {
   int32_t lik_implicit;     // 1: linearly implicit likelihood drift in the update
   double eps, t_score;
   const StepScalars* steps;   // K + 1 entries: pseudo-steps 0..K-1, then the score time
+  int32_t sparse;             // 1: W.X tiles whose weight rows are sparse gather instead
+  int32_t* sp_cnt;            // Mp_pad  weights >= kSparseTau per row (written by the softmax)
+  int32_t* sp_idx;            // Mp_pad x kSparseMax  their members, in member order
+  float* sp_w;                // Mp_pad x kSparseMax  their weights
   int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
   int32_t wx_tp, wx_te;       // W.X tiles along particles, state components
 };
@@ -117,8 +126,11 @@ void clear_stale_hip_error();
 hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g, int step,
                        hipStream_t s);
 hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ldn, hipStream_t s);
-hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
-                     int step, unsigned long long* nonfinite, hipStream_t s);
+// sparse: the degenerate-weight variant of the W.X kernel (k-step 32, one LDS stage, whatever
+// bk and st say), which gathers xhat for tiles whose weight rows are all sparse.
+hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, bool sparse,
+                     const GroupedLaunch& g, int step, unsigned long long* nonfinite,
+                     hipStream_t s);
 hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s);
 hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s);
 hipError_t launch_transpose(const ProbDev& p, hipStream_t s);

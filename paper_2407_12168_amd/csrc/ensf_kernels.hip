@@ -638,6 +638,24 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
     }
     if (P.weights_out != nullptr && j < N) P.weights_out[i * N + j] = w;
   }
+  // degenerate-weight W.X: wave 0 lists the weights >= kSparseTau in member order (ballot and
+  // prefix counts per 64 members); rows with more than kSparseMax are marked by the count
+  if (P.sparse && tid < 64) {
+    int cnt = 0;
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      const int j = j0 + tid;
+      const float w = j < N ? (float)(sL[j] * inv) : 0.0f;
+      const bool keep = w >= kSparseTau;
+      const uint64_t mask = __ballot(keep);
+      const int pos = cnt + __popcll(mask & ((1ull << tid) - 1ull));
+      if (keep && pos < kSparseMax) {
+        P.sp_idx[i * kSparseMax + pos] = j;
+        P.sp_w[i * kSparseMax + pos] = w;
+      }
+      cnt += __popcll(mask);
+    }
+    if (tid == 0) P.sp_cnt[i] = cnt;
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -646,6 +664,49 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
 // contraction over the padded members.  In this orientation register group r/4 of a lane
 // holds four consecutive components of one particle, i.e. exactly the four normals of one
 // Philox counter, so the epilogue runs from the accumulators without any exchange.
+
+// Sparse xhat of a W.X tile in the accumulator layout: for the lane's particle i and each of
+// its component quads, the sum over the row's listed members j of w_ij x_j (FP32, member
+// order), read from the caller's prior (n_members x dim, row stride dim).
+template <int WGN, int TM, int TN>
+__device__ __forceinline__ void wx_sparse_gather(const ProbDev& P, int64_t i0, int64_t e0,
+                                                 f32x16_t (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const float* X = P.X;
+  const int64_t d = P.d;
+  const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) {
+    const int64_t i = i0 + wn * TN * 32 + b * 32 + (lane & 31);
+    if (i >= P.Mp) continue;
+    const int cnt = P.sp_cnt[i];
+    for (int s = 0; s < cnt; ++s) {
+      const int j = P.sp_idx[i * kSparseMax + s];
+      const float w = P.sp_w[i * kSparseMax + s];
+      const float* xrow = X + (int64_t)j * d;
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+          const int64_t e = e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+          f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (vec && e + 3 < d) {
+            x = gload(reinterpret_cast<const f32x4*>(xrow + e));
+          } else {
+            if (e < d) x.x = xrow[e];
+            if (e + 1 < d) x.y = xrow[e + 1];
+            if (e + 2 < d) x.z = xrow[e + 2];
+            if (e + 3 < d) x.w = xrow[e + 3];
+          }
+          acc[a][b][gq * 4 + 0] = fmaf(w, x.x, acc[a][b][gq * 4 + 0]);
+          acc[a][b][gq * 4 + 1] = fmaf(w, x.y, acc[a][b][gq * 4 + 1]);
+          acc[a][b][gq * 4 + 2] = fmaf(w, x.z, acc[a][b][gq * 4 + 2]);
+          acc[a][b][gq * 4 + 3] = fmaf(w, x.w, acc[a][b][gq * 4 + 3]);
+        }
+    }
+  }
+}
 
 // Epilogue state of one W.X tile: descriptor fields and step scalars in registers.
 struct WxEpi {
@@ -729,7 +790,7 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
   }
 }
 
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE>
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE, bool SP = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
@@ -746,6 +807,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
   const int te = local / P.wx_tp;
   const int64_t e0 = (int64_t)te * BE, i0 = (int64_t)tp * BP;
 
+
   f32x16_t acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -754,7 +816,23 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  if constexpr (PREC == kFP32) {
+  // degenerate-weight variant: when every particle row of the tile has at most kSparseMax
+  // weights >= kSparseTau (listed by the softmax), xhat is gathered from those members of
+  // the FP32 prior instead of the dense product (uniform decision per tile)
+  bool sparse = false;
+  if constexpr (!SCORE && SP) {
+    if (P.sparse) {
+      int over = 0;
+      for (int t = threadIdx.x; t < BP; t += NT) {
+        const int64_t i = i0 + t;
+        over |= (i < P.Mp && P.sp_cnt[i] > kSparseMax);
+      }
+      sparse = !__syncthreads_or(over);
+    }
+  }
+  if (sparse) {
+    if constexpr (SP) wx_sparse_gather<WGN, TM, TN>(P, i0, e0, acc);
+  } else if constexpr (PREC == kFP32) {
     F32NmajLoad<BE, NT, BK> la;   // X rows (members) x components, components contiguous
     F32KmajLoad<BP, NT, BK> lb;   // W particles x members, members contiguous
     la.init(P.Xf, P.ldz, e0);
@@ -1012,7 +1090,10 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
                      dim3(64 * WGM * WGN), 0, s, g, step, nonfinite)
 #define ENSF_WX_CASE(PR, C, WGM, WGN, TM, TN)                                                \
   if (prec == PR && cfg == C) {                                                              \
-    if (score_mode)                                                                          \
+    if (sparse && !score_mode)                                                               \
+      hipLaunchKernelGGL((k_wx<PR, WGM, WGN, TM, TN, 32, 1, false, true>), dim3(g.total),    \
+                         dim3(64 * WGM * WGN), 0, s, g, step, nonfinite);                    \
+    else if (score_mode)                                                                     \
       ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 32, 2, true);                                     \
     else if (bk == 64 && st == 2)                                                            \
       ENSF_WX_LAUNCH(PR, WGM, WGN, TM, TN, 64, 2, false);                                    \
@@ -1039,8 +1120,9 @@ hipError_t launch_gram(int prec, int cfg, int bk, int st, const GroupedLaunch& g
   ENSF_WX_CASE(PR, kWx128e, 2, 4, 2, 1)     \
   ENSF_WX_CASE(PR, kWx128f, 4, 2, 1, 2)
 
-hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, const GroupedLaunch& g,
-                     int step, unsigned long long* nonfinite, hipStream_t s) {
+hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, bool sparse,
+                     const GroupedLaunch& g, int step, unsigned long long* nonfinite,
+                     hipStream_t s) {
   if (g.total <= 0) return hipSuccess;
   ENSF_WX_ALL(kFP32)
   ENSF_WX_ALL(kBF16X3)

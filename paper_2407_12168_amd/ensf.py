@@ -33,7 +33,8 @@ class ensf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("obs_op", ctypes.c_int32),
                 ("eps_alpha", ctypes.c_double), ("spread_relax", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p), ("lik_step", ctypes.c_int32)]
+                ("tune_cache", ctypes.c_char_p), ("lik_step", ctypes.c_int32),
+                ("wx_sparse", ctypes.c_int32)]
 
 
 class ensf_problem(ctypes.Structure):
@@ -130,7 +131,8 @@ def ensf_default_options():
 
 
 def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=0.0,
-                use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE, lik_step="explicit"):
+                use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE, lik_step="explicit",
+                wx_sparse=False):
     o = ensf_default_options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
@@ -140,6 +142,7 @@ def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=
     o.device = device
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.lik_step = LIK_STEPS[lik_step] if isinstance(lik_step, str) else int(lik_step)
+    o.wx_sparse = 1 if wx_sparse else 0
     h = ctypes.c_void_p()
     _check(_lib().ensf_create(ctypes.byref(o), ctypes.byref(h)), "ensf_create")
     return h
