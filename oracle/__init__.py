@@ -18,5 +18,5 @@ Contents
            and the Kalman posterior it is compared with.
   conv, sqg
            the convolutional forecast surrogate in FP64 and a pseudo-spectral SQG
-           stepper (Sec. II-B) used as truth generator and judge.
+           stepper (Sec. II-B) used as truth generator and as the reference forecast.
 """
