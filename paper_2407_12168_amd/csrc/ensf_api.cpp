@@ -881,7 +881,7 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs_in, i
   // side fixed, then the W.X side with the Gram side fixed, then the Gram side again.
   TileChoice best = heuristic_tiles(p.n_members, p.n_particles);
   float best_ms = INFINITY;
-  const double scales[] = {0.5, 1.0, 2.0};
+  const double scales[] = {0.25, 0.5, 1.0, 2.0, 4.0};
   for (int pass = 0; pass < 3 && st == ENSF_OK; ++pass) {
     const TileChoice base = best;
     if (pass != 1) {
