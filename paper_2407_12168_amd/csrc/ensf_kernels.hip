@@ -581,13 +581,30 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
   const float* prow = P.part + i * P.ldn;
   const int tid = threadIdx.x;
 
+  // Partials s0, s0 + ds, ... < S of quad q summed in that order (FP64); the loads are
+  // issued eight at a time ahead of their additions, which keep the order.
+  auto sum_quads = [&](int q, int s0, int ds, double& a0, double& a1, double& a2, double& a3) {
+    const float* pq = prow + 4 * q;
+    int s = s0;
+    for (; s + 7 * ds < S; s += 8 * ds) {
+      f32x4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = gload(reinterpret_cast<const f32x4*>(pq + (int64_t)(s + u * ds) * pstride));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 += v[u].x; a1 += v[u].y; a2 += v[u].z; a3 += v[u].w;
+      }
+    }
+    for (; s < S; s += ds) {
+      const f32x4 v = gload(reinterpret_cast<const f32x4*>(pq + (int64_t)s * pstride));
+      a0 += v.x; a1 += v.y; a2 += v.z; a3 += v.w;
+    }
+  };
   if (nq >= 256) {
     for (int q = tid; q < nq; q += 256) {
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      for (int s = 0; s < S; ++s) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(prow + s * pstride + 4 * q);
-        a0 += v.x; a1 += v.y; a2 += v.z; a3 += v.w;
-      }
+      sum_quads(q, 0, 1, a0, a1, a2, a3);
       sL[4 * q + 0] = a0; sL[4 * q + 1] = a1; sL[4 * q + 2] = a2; sL[4 * q + 3] = a3;
     }
   } else {
@@ -595,10 +612,7 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
     const int grp = tid / nq, q = tid % nq;
     if (grp < G) {
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      for (int s = grp; s < S; s += G) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(prow + s * pstride + 4 * q);
-        a0 += v.x; a1 += v.y; a2 += v.z; a3 += v.w;
-      }
+      sum_quads(q, grp, G, a0, a1, a2, a3);
       double* o = sG + 4 * (grp * nq + q);
       o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
     }
