@@ -215,8 +215,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the analysis shards over particles or "
-              "filters; no multi-GPU path is built).", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the analysis would shard over particles or "
+              "filters; there is no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
 
     if a.config == 5:
