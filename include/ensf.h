@@ -56,7 +56,7 @@ typedef enum {
   ENSF_ENOMEM = 2,        /* device or pinned host allocation failed */
   ENSF_EHIP = 3,          /* HIP runtime or launch error */
   ENSF_ENONFINITE = 4,    /* a particle became NaN or Inf (from ensf_sync_status) */
-  ENSF_EUNSUPPORTED = 5   /* valid request this build does not implement */
+  ENSF_EUNSUPPORTED = 5   /* valid request that the library does not implement */
 } ensf_status;
 
 typedef enum {
