@@ -223,12 +223,23 @@ def test_out_of_range_observation_and_nonfinite_reported(dev):
 # Gaussian prior, linear observation, large ensemble: the GPU particles must follow the
 # closed-form recursion of the scheme (and the Kalman gap is reported)
 
+def quantile_members_2d(mu, n, seed):
+    """n members of N(mu, I_2): both components at the normal quantiles (j + 1/2)/n, the
+    second in a seeded random order.  Each component's empirical law is within O(1/n) of
+    the Gaussian, so the Monte-Carlo score adds no offset of the size of the particles'
+    sampling error; the two components are uncorrelated to O(1/sqrt(n)), which moves the
+    unobserved component's mean by about 1e-2 of a standard error here."""
+    from scipy.stats import norm
+    q = mu + norm.ppf((np.arange(n) + 0.5) / n)
+    perm = np.random.default_rng(seed).permutation(n)
+    return np.stack([q, q[perm]], axis=1).astype(np.float32)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_linear_gaussian_large_ensemble(dev, precision):
     from oracle import linear_gaussian as lg
     N, M, K, sig, y = 16384, 4096, 200, 1.0, 1.0
-    rng = np.random.default_rng(21)
-    X = (0.3 + rng.standard_normal((N, 2))).astype(np.float32)
+    X = quantile_members_2d(0.3, N, seed=21)
     p = workloads.Problem(X=X, truth=None, obs_idx=np.array([0], np.int32),
                           obs_val=np.array([y], np.float32), sigma_o=sig, n_steps=K, seed=9,
                           obs_op="linear")
@@ -240,8 +251,8 @@ def test_linear_gaussian_large_ensemble(dev, precision):
                   else (Xd[:, e].mean(), Xd[:, e].var(ddof=1)))
         print(f"{precision} e{e}: mean {Z[:, e].mean():.4f} recursion {m:.4f} Kalman {km:.4f}; "
               f"var {Z[:, e].var(ddof=1):.4f} recursion {v:.4f} Kalman {kv:.4f}")
-        assert abs(Z[:, e].mean() - m) < 4 * np.sqrt(v / M) + 0.02
-        assert abs(Z[:, e].var(ddof=1) / v - 1) < 4 * np.sqrt(2.0 / M) + 0.05
+        assert abs(Z[:, e].mean() - m) < 4 * np.sqrt(v / M)
+        assert abs(Z[:, e].var(ddof=1) / v - 1) < 4 * np.sqrt(2.0 / (M - 1))
 
 
 def test_no_observations_and_linear_operator_match_oracle(dev):

@@ -12,22 +12,24 @@ import workloads
 from oracle import ensf
 from oracle import linear_gaussian as lg
 
+from test_oracle_linear_gaussian import quantile_members
+
 
 @pytest.mark.parametrize("sigma_o,y,K,seed", [(0.05, 0.8, 100, 11), (0.1, -0.4, 50, 12)])
 def test_implicit_particles_follow_discrete_recursion(sigma_o, y, K, seed):
-    # dt >= sigma_o^2 here: the explicit scheme diverges, the implicit one must not
+    # dt >= sigma_o^2 here: the explicit scheme diverges, the implicit one must not.
+    # Members at the normal quantiles (see test_oracle_linear_gaussian): no allowance
+    # beyond the particles' own sampling error.
     N, P = 2048, 1024
-    rng = np.random.default_rng(seed)
-    X = 0.3 + rng.standard_normal((N, 2))
+    X = quantile_members(0.3, N)
     Z = ensf.analysis(X, np.array([0]), np.array([y]), sigma_o, K, seed=seed, obs_op="linear",
                       n_particles=P, chunk=256, lik_step="implicit")
-    for e, (A, B) in enumerate([(y / sigma_o ** 2, 1.0 / sigma_o ** 2), (0.0, 0.0)]):
-        mh, s2h = X[:, e].mean(), X[:, e].var(ddof=1)
-        m, v = lg.em_recursion(mh, s2h, A, B, K, lik_step="implicit")
-        print(f"e={e}: particles {Z[:, e].mean():.4f} / {Z[:, e].var(ddof=1):.5f}, "
-              f"recursion {m:.4f} / {v:.5f}")
-        assert abs(Z[:, e].mean() - m) < 4 * np.sqrt(v / P) + 0.02
-        assert abs(Z[:, e].var(ddof=1) / v - 1.0) < 4 * np.sqrt(2.0 / P) + 0.05
+    mh, s2h = X[:, 0].mean(), X[:, 0].var(ddof=1)
+    m, v = lg.em_recursion(mh, s2h, y / sigma_o ** 2, 1.0 / sigma_o ** 2, K, lik_step="implicit")
+    print(f"particles {Z[:, 0].mean():.4f} / {Z[:, 0].var(ddof=1):.5f}, "
+          f"recursion {m:.4f} / {v:.5f}")
+    assert abs(Z[:, 0].mean() - m) < 4 * np.sqrt(v / P)
+    assert abs(Z[:, 0].var(ddof=1) / v - 1.0) < 4 * np.sqrt(2.0 / (P - 1))
 
 
 def test_implicit_recursion_stable_where_explicit_diverges():
