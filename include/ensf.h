@@ -33,10 +33,18 @@
  *     row-major float32: the prior X is n_members x dim, particles n_particles x dim.
  *   - Calls are asynchronous on the given stream (a hipStream_t passed as void*;
  *     NULL is the default stream): they validate, enqueue and return.  A context
- *     must not be used by two threads at once.
+ *     must not be used by two threads at once.  Calls on one context run in call
+ *     order on the device even when they name different streams: a call on another
+ *     stream than the previous call's makes its stream wait for that call first (the
+ *     context's workspace is shared by its calls).
+ *   - Observations with the same index add (independent likelihood factors).  Their sums
+ *     are formed exactly in 64-bit fixed point (each value rounded to within 2^-31 of
+ *     the largest |y|), so results do not depend on the order of the observations or
+ *     of the device's work: runs are bit-reproducible.
  *   - Argument errors return ENSF_EINVAL synchronously and enqueue nothing.
- *     Launch failures return ENSF_EHIP.  Observation indices outside [0, dim) are
- *     skipped on the device and reported by ensf_sync_status as ENSF_EINVAL;
+ *     Launch failures return ENSF_EHIP.  Observations with an index outside [0, dim)
+ *     or a non-finite value are skipped on the device and reported by ensf_sync_status
+ *     as ENSF_EINVAL;
  *     non-finite particle values are counted and reported there as ENSF_ENONFINITE.
  */
 #ifndef ENSF_H
@@ -122,7 +130,7 @@ ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out);
 /* Analysis step (Sec. III-A-2, eqs. 7, 11-17): writes the n_particles analysis particles
    into d_post.  d_prior is read on every pseudo-step and must stay valid and unchanged
    until the stream reaches the end of this call.  n_obs = 0 runs without observations
-   (d_obs_idx / d_obs_val may then be NULL).  Limits: 1 <= n_members <= 16384,
+   (d_obs_idx / d_obs_val may then be NULL); n_obs <= 2^31 - 1.  Limits: 1 <= n_members <= 16384,
    n_particles >= 1, dim >= 1, n_steps >= 1. */
 ensf_status ensf_analysis(ensf_ctx* ctx,
                           const float* d_prior, int32_t n_members, int64_t dim,
@@ -158,9 +166,10 @@ ensf_status ensf_rng_normal(uint64_t seed, uint32_t filter_id, uint32_t step, ui
 ensf_status ensf_ensemble_stats(const float* d_ens, int32_t n, int64_t dim,
                                 float* d_mean, float* d_spread, void* stream);
 
-/* Waits for the last stream used by ctx and reports device-side conditions of the
-   calls since the previous ensf_sync_status: ENSF_EINVAL for out-of-range observation
-   indices, ENSF_ENONFINITE (with *nonfinite_count set) for NaN/Inf particles. */
+/* Waits for the last stream used by ctx (and so for every earlier call on ctx) and reports
+   device-side conditions of the calls since the previous ensf_sync_status: ENSF_EINVAL for
+   invalid observations (index outside [0, dim) or non-finite value), ENSF_ENONFINITE (with
+   *nonfinite_count set) for NaN/Inf particles. */
 ensf_status ensf_sync_status(ensf_ctx* ctx, int64_t* nonfinite_count);
 
 /* Times candidate kernel variants on the given problem (running it several times on

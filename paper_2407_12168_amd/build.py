@@ -7,6 +7,7 @@ Every HIP translation unit is compiled with packed-FP32 instruction selection di
 form those instructions either).
 """
 import argparse
+import hashlib
 import os
 import subprocess
 import sys
@@ -34,21 +35,48 @@ def sources():
     return out
 
 
-def _compile(src, is_hip, hipcc):
+def _headers():
+    hs = [os.path.join(CSRC, n) for n in os.listdir(CSRC) if n.endswith(".h")]
+    inc = os.path.join(ROOT, "include")
+    return hs + [os.path.join(inc, n) for n in os.listdir(inc) if n.endswith(".h")]
+
+
+def _digest(src, cmd):
+    """Hash of the command and of the source and header texts as read before compiling."""
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for f in [src] + sorted(_headers()):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _compile(src, is_hip, hipcc, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [hipcc] + COMMON + (HIP_FLAGS if is_hip else [f"--offload-arch={ARCH}"]) + ["-c", src, "-o", obj]
+    stamp = obj + ".sha256"
+    digest = _digest(src, cmd)
+    if incremental and os.path.exists(obj) and os.path.exists(stamp):
+        with open(stamp) as fh:
+            if fh.read().strip() == digest:
+                return obj
+    if os.path.exists(stamp):
+        os.remove(stamp)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    with open(stamp, "w") as fh:
+        fh.write(digest)
     return obj
 
 
-def build(jobs=4, verbose=False):
+def build(jobs=4, verbose=False, incremental=False):
+    """Compiles every source (incremental=True: only those whose text, header texts or
+    command changed since their object file was built) and links libensf.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: _compile(s[0], s[1], hipcc), srcs))
+        objs = list(ex.map(lambda s: _compile(s[0], s[1], hipcc, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
@@ -64,6 +92,8 @@ def build(jobs=4, verbose=False):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only sources whose text, headers or command changed")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, incremental=a.incremental)
     sys.exit(0)

@@ -99,6 +99,7 @@ struct ensf_ctx {
   bool tab_event_pending = false;
   unsigned long long* d_counters = nullptr;  // [0] non-finite values, [1] bad obs indices
   hipStream_t cap_stream = nullptr;
+  hipEvent_t done_event = nullptr;   // recorded at the end of every call, on its stream
   hipStream_t last_stream = nullptr;
   bool has_last_stream = false;
   GraphKey gkey;
@@ -155,7 +156,7 @@ ensf_status validate(const ensf_problem& p) {
   if (p.n_members < 1 || p.n_members > kMaxMembers) return ENSF_EINVAL;
   if (p.n_particles < 1 || p.dim < 1 || p.n_steps < 1) return ENSF_EINVAL;
   if ((int64_t)p.dim * 4 / 4 != p.dim || p.dim > (int64_t(1) << 34)) return ENSF_EINVAL;
-  if (p.n_obs < 0) return ENSF_EINVAL;
+  if (p.n_obs < 0 || p.n_obs > INT32_MAX) return ENSF_EINVAL;
   if (p.n_obs > 0) {
     if (!p.d_obs_idx || !p.d_obs_val) return ENSF_EINVAL;
     if (!(p.obs_sigma > 0.0f) || !std::isfinite(p.obs_sigma)) return ENSF_EINVAL;
@@ -198,7 +199,7 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
   P.seed_hi = (uint32_t)(p.seed >> 32);
   P.filter = p.filter_id;
-  P.inv_sig2 = p.n_obs > 0 ? (float)(1.0 / ((double)p.obs_sigma * (double)p.obs_sigma)) : 0.0f;
+  P.inv_sig2_d = p.n_obs > 0 ? 1.0 / ((double)p.obs_sigma * (double)p.obs_sigma) : 0.0;
   P.obs_op = opt.obs_op;
   P.lik_implicit = opt.lik_step == ENSF_LIK_IMPLICIT ? 1 : 0;
   P.sparse = opt.wx_sparse ? 1 : 0;
@@ -247,6 +248,7 @@ size_t layout_problem(ProbDev& P, const ensf_problem& p, int prec, const TileCho
   P.sp_cnt = reinterpret_cast<int32_t*>(take((size_t)P.Mp_pad * 4));
   P.sp_idx = reinterpret_cast<int32_t*>(take((size_t)P.Mp_pad * kSparseMax * 4));
   P.sp_w = reinterpret_cast<float*>(take((size_t)P.Mp_pad * kSparseMax * 4));
+  P.ob_acc = reinterpret_cast<long long*>(take((size_t)(P.ldz + 1) * 8));
   return round_up(off, kAlign);
 }
 
@@ -464,6 +466,7 @@ ensf_status zero_problem(const ProbDev& P, int prec, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(P.xnorm, 0, (size_t)P.ldn * 4, s));
   HIP_TRY(hipMemsetAsync(P.A, 0, (size_t)P.ldz * 4, s));
   HIP_TRY(hipMemsetAsync(P.B, 0, (size_t)P.ldz * 4, s));
+  if (P.n_obs > 0) HIP_TRY(hipMemsetAsync(P.ob_acc, 0, (size_t)(P.ldz + 1) * 8, s));
   HIP_TRY(hipMemsetAsync(P.sp_cnt, 0, (size_t)P.Mp_pad * 4, s));
   return ENSF_OK;
 }
@@ -610,6 +613,22 @@ ensf_status run_steps(ensf_ctx* c, const Plan& plan, const Uploaded& u, hipStrea
   return ENSF_OK;
 }
 
+// Every call on a context rewrites the context's workspace and descriptor table.  A call on
+// a stream other than the previous call's first makes its stream wait for the end of that
+// call (done_event), so calls on one context run in call order whatever streams they use.
+ensf_status order_after_previous(ensf_ctx* c, hipStream_t s) {
+  if (c->has_last_stream && c->last_stream != s)
+    HIP_TRY(hipStreamWaitEvent(s, c->done_event, 0));
+  return ENSF_OK;
+}
+
+ensf_status mark_call_end(ensf_ctx* c, hipStream_t s) {
+  HIP_TRY(hipEventRecord(c->done_event, s));
+  c->last_stream = s;
+  c->has_last_stream = true;
+  return ENSF_OK;
+}
+
 ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, hipStream_t s,
                           const TileChoice* force) {
   for (const auto& p : probs) {
@@ -618,8 +637,10 @@ ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, h
   }
   clear_stale_hip_error();
   HIP_TRY(hipSetDevice(c->device));
+  ensf_status st = order_after_previous(c, s);
+  if (st != ENSF_OK) return st;
   Plan plan;
-  ensf_status st = build_plan(c, probs, plan, force);
+  st = build_plan(c, probs, plan, force);
   if (st != ENSF_OK) return st;
   st = ensure_workspace(c, plan.ws_needed);
   if (st != ENSF_OK) return st;
@@ -640,9 +661,7 @@ ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, h
       HIP_TRY(launch_relax(P, c->opt.spread_relax, s));
     HIP_TRY(launch_store_post(P, s));
   }
-  c->last_stream = s;
-  c->has_last_stream = true;
-  return ENSF_OK;
+  return mark_call_end(c, s);
 }
 
 // ----- tune cache: a flat JSON object {"key": [gram, wx, split_scale], ...}
@@ -735,6 +754,7 @@ ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out) {
   if (e == hipSuccess) e = hipMemset(c->d_counters, 0, 2 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_event, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done_event, hipEventDisableTiming);
   if (e != hipSuccess) {
     ensf_destroy(c);
     return hip_fail(e);
@@ -774,6 +794,8 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   clear_stale_hip_error();
   HIP_TRY(hipSetDevice(ctx->device));
+  st = order_after_previous(ctx, s);
+  if (st != ENSF_OK) return st;
   std::vector<ensf_problem> probs{p};
   Plan plan;
   st = build_plan(ctx, probs, plan, nullptr);
@@ -799,9 +821,7 @@ ensf_status ensf_score(ensf_ctx* ctx, const float* d_prior, int32_t n_members, i
   HIP_TRY(launch_gram(prec, tiles.gram, tiles.gram_bk, tiles.gram_st, u.gram[0], -1, s));
   HIP_TRY(launch_softmax(prec, u.rows, -1, plan.max_ldn, s));
   HIP_TRY(launch_wx(prec, tiles.wx, 32, 2, true, false, u.wx[0], -1, ctx->d_counters, s));
-  ctx->last_stream = s;
-  ctx->has_last_stream = true;
-  return ENSF_OK;
+  return mark_call_end(ctx, s);
 }
 
 ensf_status ensf_rng_normal(uint64_t seed, uint32_t filter_id, uint32_t step, uint32_t particle,
@@ -961,6 +981,7 @@ ensf_status ensf_destroy(ensf_ctx* ctx) {
   if (ctx->d_counters) (void)hipFree(ctx->d_counters);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->tab_event) (void)hipEventDestroy(ctx->tab_event);
+  if (ctx->done_event) (void)hipEventDestroy(ctx->done_event);
   delete ctx;
   return ENSF_OK;
 }

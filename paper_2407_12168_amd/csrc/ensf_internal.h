@@ -53,7 +53,7 @@ struct ProbDev {
   int64_t d, ldz, n_obs, kchunk;
   int32_t N, Mp, Mp_pad, N_pad, ldn, S, K;
   uint32_t seed_lo, seed_hi, filter;
-  float inv_sig2;
+  double inv_sig2_d;         // 1 / obs_sigma^2 (0 without observations)
   int32_t obs_op;
   int32_t lik_implicit;     // 1: linearly implicit likelihood drift in the update
   double eps, t_score;
@@ -62,6 +62,8 @@ struct ProbDev {
   int32_t* sp_cnt;            // Mp_pad  weights >= kSparseTau per row (written by the softmax)
   int32_t* sp_idx;            // Mp_pad x kSparseMax  their members, in member order
   float* sp_w;                // Mp_pad x kSparseMax  their weights
+  long long* ob_acc;          // ldz + 1: fixed-point sums of y per component, then the
+                              // float bits of the largest |y| (densification)
   int32_t gram_tm, gram_tn;   // Gram tiles along particles, members
   int32_t wx_tp, wx_te;       // W.X tiles along particles, state components
 };
@@ -131,6 +133,7 @@ hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ld
 hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, bool sparse,
                      const GroupedLaunch& g, int step, unsigned long long* nonfinite,
                      hipStream_t s);
+// Observation densification (ensf_densify.hip): deterministic A and B, any duplicates.
 hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s);
 hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s);
 hipError_t launch_transpose(const ProbDev& p, hipStream_t s);

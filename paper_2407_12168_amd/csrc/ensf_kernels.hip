@@ -914,18 +914,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 // ----------------------------------------------------------------------------------------
 // One-off kernels of an analysis
 
-__global__ void k_densify(ProbDev P, unsigned long long* bad_obs) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= P.n_obs) return;
-  const int64_t e = P.obs_idx[m];
-  if (e < 0 || e >= P.d) {
-    atomicAdd(bad_obs, 1ull);
-    return;
-  }
-  atomicAdd(P.A + e, P.obs_val[m] * P.inv_sig2);
-  atomicAdd(P.B + e, P.inv_sig2);
-}
-
 // Member row j: |x_j|^2 (FP64 accumulation) and the padded FP32 or bf16 hi/lo copy.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_prep_rows(ProbDev P) {
@@ -1166,12 +1154,6 @@ hipError_t set_softmax_smem_limit(size_t bytes) {
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k_softmax<kBF16>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s) {
-  if (p.n_obs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_densify, dim3(blocks_for(p.n_obs, 256)), dim3(256), 0, s, p, bad_obs);
-  return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s) {

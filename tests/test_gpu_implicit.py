@@ -51,8 +51,10 @@ def test_literal_k_config1_full_trajectory(dev, c1_case, precision):
     got = _run(dev, p, precision)
     err = O.rel_l2(got, want)
     mean_err = O.rel_l2(got.mean(0), want.mean(0))
-    print(f"c1 K={p.n_steps} implicit {precision}: particles rel-L2 {err:.2e}, mean {mean_err:.2e}")
-    assert err <= 1e-3 and mean_err <= 1e-3
+    elem = np.abs(got - want).max() / np.abs(want).max()
+    print(f"c1 K={p.n_steps} implicit {precision}: particles rel-L2 {err:.2e}, mean {mean_err:.2e}, "
+          f"max elementwise {elem:.2e}")
+    assert err <= 1e-3 and mean_err <= 1e-3 and elem <= 1e-3
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -63,19 +65,10 @@ def test_literal_k_config2_particle_subset(dev, precision):
     want = O.analysis(p.X, p.obs_idx, p.obs_val, p.sigma_o, p.n_steps, p.seed,
                       particle_ids=rows, lik_step="implicit")
     err = O.rel_l2(got[rows], want)
-    print(f"c2 K={p.n_steps} implicit {precision} particles {rows}: rel-L2 {err:.2e}")
-    assert err <= 1e-3
-
-
-def test_literal_k_config3_split_particle_subset(dev):
-    p = workloads.config_problem(3)          # K = 200, sigma_o = 0.02, all observed
-    got = _run(dev, p, "bf16x3")
-    rows = [0, 1023]
-    want = O.analysis(p.X, p.obs_idx, p.obs_val, p.sigma_o, p.n_steps, p.seed,
-                      particle_ids=rows, lik_step="implicit", chunk=2)
-    err = O.rel_l2(got[rows], want)
-    print(f"c3 K={p.n_steps} implicit bf16x3 particles {rows}: rel-L2 {err:.2e}")
-    assert err <= 1e-3
+    elem = np.abs(got[rows] - want).max() / np.abs(want).max()
+    print(f"c2 K={p.n_steps} implicit {precision} particles {rows}: rel-L2 {err:.2e}, "
+          f"max elementwise {elem:.2e}")
+    assert err <= 1e-3 and elem <= 1e-3
 
 
 def test_implicit_linear_gaussian_where_explicit_diverges(dev):
