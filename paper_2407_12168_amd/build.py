@@ -9,6 +9,7 @@ form those instructions either).
 import argparse
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -35,16 +36,29 @@ def sources():
     return out
 
 
-def _headers():
-    hs = [os.path.join(CSRC, n) for n in os.listdir(CSRC) if n.endswith(".h")]
-    inc = os.path.join(ROOT, "include")
-    return hs + [os.path.join(inc, n) for n in os.listdir(inc) if n.endswith(".h")]
+_QUOTE_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _local_headers(src):
+    """The project headers `src` includes with #include "...", transitively."""
+    seen, todo = set(), [src]
+    while todo:
+        f = todo.pop()
+        with open(f) as fh:
+            names = _QUOTE_INCLUDE.findall(fh.read())
+        for n in names:
+            h = os.path.normpath(os.path.join(os.path.dirname(f), n))
+            if os.path.exists(h) and h not in seen:
+                seen.add(h)
+                todo.append(h)
+    return sorted(seen)
 
 
 def _digest(src, cmd):
-    """Hash of the command and of the source and header texts as read before compiling."""
+    """Hash of the command and of the source and included header texts as read before
+    compiling."""
     h = hashlib.sha256(" ".join(cmd).encode())
-    for f in [src] + sorted(_headers()):
+    for f in [src] + _local_headers(src):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
