@@ -64,7 +64,9 @@ typedef enum {
   ENSF_ENOMEM = 2,        /* device or pinned host allocation failed */
   ENSF_EHIP = 3,          /* HIP runtime or launch error */
   ENSF_ENONFINITE = 4,    /* a particle became NaN or Inf (from ensf_sync_status) */
-  ENSF_EUNSUPPORTED = 5   /* valid request that the library does not implement */
+  ENSF_EUNSUPPORTED = 5,  /* valid request that the library does not implement */
+  ENSF_ESCRATCH = 6       /* ensf_analysis_noalloc: the problem needs more than the
+                             ENSF_NOALLOC_SCRATCH_BYTES of the library's static buffer */
 } ensf_status;
 
 typedef enum {
@@ -198,6 +200,37 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs, int3
    the last reset (ensf_profile_phases(ctx, 1) resets). */
 ensf_status ensf_profile_phases(ensf_ctx* ctx, int32_t enable);
 ensf_status ensf_phase_times(ensf_ctx* ctx, double* ms, int64_t* count);
+
+/* Size in bytes of the device buffer behind ensf_analysis_noalloc: one statically allocated
+   array in the library's device code, held by every GPU the entry point runs on until the
+   process ends. */
+#define ENSF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code being captured into a HIP graph,
+   tight serving loops, harnesses that forbid hipMalloc): ensf_analysis without a context.
+   Every buffer of the analysis (workspace, descriptor and step tables, counters) is carved
+   out of the library's static scratch array of ENSF_NOALLOC_SCRATCH_BYTES on the current
+   device of opt->device; nothing is allocated, no memset or host-to-device copy is enqueued
+   (tables travel as kernel arguments, buffers are cleared by kernels), and the pseudo-time
+   loop is launched eagerly on the stream.  opt gives precision, observation operator,
+   likelihood step, eps, spread relaxation, degenerate-weight W.X and device (NULL = the
+   defaults of ensf_default_options); use_graph and tune_cache are ignored: tiles come from
+   the built-in heuristic, the choice a context makes without a tune table, so results are
+   bit-identical to ensf_analysis on such a context.  Arguments as in ensf_analysis.
+   d_counters: NULL, or a caller-owned device array of two uint64 to which the call adds the
+   number of non-finite particle values ([0]) and of skipped invalid observations ([1]).
+   Errors: ENSF_EINVAL (as ensf_analysis), ENSF_ESCRATCH if the problem needs more than the
+   scratch size (synchronously, nothing enqueued), ENSF_EHIP.  All calls on one GPU share its
+   scratch array, which keeps the last call's contents: calls that can overlap on one GPU
+   (other streams, other threads) race and must be serialised by the caller.  The first call
+   on each device looks the array up there (hipGetSymbolAddress). */
+ensf_status ensf_analysis_noalloc(const ensf_options* opt,
+                                  const float* d_prior, int32_t n_members, int64_t dim,
+                                  float* d_post, int32_t n_particles,
+                                  const int32_t* d_obs_idx, const float* d_obs_val,
+                                  int64_t n_obs, float obs_sigma, int32_t n_steps,
+                                  uint64_t seed, uint32_t filter_id,
+                                  unsigned long long* d_counters, void* stream);
 
 /* Frees the context and its workspace.  NULL is a no-op. */
 ensf_status ensf_destroy(ensf_ctx* ctx);

@@ -14,6 +14,7 @@
 
 #include "../../include/ensf.h"
 #include "ensf_internal.h"
+#include "ensf_run.h"
 
 namespace ensf {
 hipError_t set_softmax_smem_limit(size_t bytes);
@@ -395,18 +396,15 @@ struct Uploaded {
   std::vector<GroupedLaunch> gram, wx;   // one per group
 };
 
-ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& u) {
+// Lays the descriptor table, prefix arrays and step tables of `plan` out for the device
+// address d_tab: writes them into the host buffer h (when not null) and fills u with device
+// pointers.  Returns the table's size in bytes.
+size_t stage_plan(const Plan& plan, char* h, char* d_tab, Uploaded& u) {
   const int np = (int)plan.desc.size();
   auto al = [](size_t v) { return (size_t)round_up((int64_t)v, 256); };
-  size_t bytes = al(sizeof(ProbDev) * np) + al(sizeof(int32_t) * (np + 1));
-  for (const Group& G : plan.groups) bytes += 2 * al(sizeof(int32_t) * (G.count + 1));
-  for (const ProbDev& P : plan.desc) bytes += al(sizeof(StepScalars) * (P.K + 1));
-  ensf_status st = ensure_table(c, bytes);
-  if (st != ENSF_OK) return st;
-  if (c->tab_event_pending) HIP_TRY(hipEventSynchronize(c->tab_event));
   size_t off = 0;
   auto put = [&](const void* src, size_t n) {
-    memcpy(c->h_tab + off, src, n);
+    if (h) memcpy(h + off, src, n);
     const size_t at = off;
     off += al(n);
     return at;
@@ -429,45 +427,56 @@ ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& 
       table[k] = host_step_scalars(1.0 - (double)k * (1.0 / (double)P.K), P.eps, P.K);
     table[P.K] = host_step_scalars(P.t_score, P.eps, P.K);
     const size_t o = put(table.data(), sizeof(StepScalars) * (P.K + 1));
-    reinterpret_cast<ProbDev*>(c->h_tab + o_desc)[f].steps =
-        reinterpret_cast<const StepScalars*>(c->d_tab + o);
+    if (h)
+      reinterpret_cast<ProbDev*>(h + o_desc)[f].steps =
+          reinterpret_cast<const StepScalars*>(d_tab + o);
   }
-  HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, off, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(c->tab_event, s));
-  c->tab_event_pending = true;
-  const ProbDev* d = reinterpret_cast<const ProbDev*>(c->d_tab + o_desc);
-  u.rows = GroupedLaunch{d, reinterpret_cast<const int32_t*>(c->d_tab + o_rows), np,
+  const ProbDev* d = reinterpret_cast<const ProbDev*>(d_tab + o_desc);
+  u.rows = GroupedLaunch{d, reinterpret_cast<const int32_t*>(d_tab + o_rows), np,
                          plan.pre_rows[np]};
   u.gram.clear();
   u.wx.clear();
   for (size_t g = 0; g < plan.groups.size(); ++g) {
     const Group& G = plan.groups[g];
     u.gram.push_back(GroupedLaunch{d + G.first,
-                                   reinterpret_cast<const int32_t*>(c->d_tab + o_grp[g].first),
+                                   reinterpret_cast<const int32_t*>(d_tab + o_grp[g].first),
                                    G.count, G.pre_gram[G.count]});
     u.wx.push_back(GroupedLaunch{d + G.first,
-                                 reinterpret_cast<const int32_t*>(c->d_tab + o_grp[g].second),
+                                 reinterpret_cast<const int32_t*>(d_tab + o_grp[g].second),
                                  G.count, G.pre_wx[G.count]});
   }
+  return off;
+}
+
+ensf_status upload_plan(ensf_ctx* c, const Plan& plan, hipStream_t s, Uploaded& u) {
+  ensf_status st = ensure_table(c, stage_plan(plan, nullptr, nullptr, u));
+  if (st != ENSF_OK) return st;
+  if (c->tab_event_pending) HIP_TRY(hipEventSynchronize(c->tab_event));
+  const size_t bytes = stage_plan(plan, c->h_tab, c->d_tab, u);
+  HIP_TRY(hipMemcpyAsync(c->d_tab, c->h_tab, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(c->tab_event, s));
+  c->tab_event_pending = true;
   return ENSF_OK;
 }
 
+// Workspace regions that must start at zero (padding, accumulators), cleared by a fill
+// kernel rather than hipMemsetAsync so that the enqueued work may be captured in a graph.
 ensf_status zero_problem(const ProbDev& P, int prec, hipStream_t s) {
-  HIP_TRY(hipMemsetAsync(P.Z, 0, (size_t)P.Mp_pad * P.ldz * 4, s));
+  HIP_TRY(launch_fill_zero(P.Z, (size_t)P.Mp_pad * P.ldz * 4, s));
   if (prec == kFP32) {
-    HIP_TRY(hipMemsetAsync(P.Xf, 0, (size_t)P.N_pad * P.ldz * 4, s));
-    HIP_TRY(hipMemsetAsync(P.W, 0, (size_t)P.Mp_pad * P.ldn * 4, s));
+    HIP_TRY(launch_fill_zero(P.Xf, (size_t)P.N_pad * P.ldz * 4, s));
+    HIP_TRY(launch_fill_zero(P.W, (size_t)P.Mp_pad * P.ldn * 4, s));
   } else {
-    HIP_TRY(hipMemsetAsync(P.Xh, 0, (size_t)P.N_pad * P.ldz * 2, s));
-    HIP_TRY(hipMemsetAsync(P.Xl, 0, (size_t)P.N_pad * P.ldz * 2, s));
-    HIP_TRY(hipMemsetAsync(P.Wh, 0, (size_t)P.Mp_pad * P.ldn * 2, s));
-    HIP_TRY(hipMemsetAsync(P.Wl, 0, (size_t)P.Mp_pad * P.ldn * 2, s));
+    HIP_TRY(launch_fill_zero(P.Xh, (size_t)P.N_pad * P.ldz * 2, s));
+    HIP_TRY(launch_fill_zero(P.Xl, (size_t)P.N_pad * P.ldz * 2, s));
+    HIP_TRY(launch_fill_zero(P.Wh, (size_t)P.Mp_pad * P.ldn * 2, s));
+    HIP_TRY(launch_fill_zero(P.Wl, (size_t)P.Mp_pad * P.ldn * 2, s));
   }
-  HIP_TRY(hipMemsetAsync(P.xnorm, 0, (size_t)P.ldn * 4, s));
-  HIP_TRY(hipMemsetAsync(P.A, 0, (size_t)P.ldz * 4, s));
-  HIP_TRY(hipMemsetAsync(P.B, 0, (size_t)P.ldz * 4, s));
-  if (P.n_obs > 0) HIP_TRY(hipMemsetAsync(P.ob_acc, 0, (size_t)(P.ldz + 1) * 8, s));
-  HIP_TRY(hipMemsetAsync(P.sp_cnt, 0, (size_t)P.Mp_pad * 4, s));
+  HIP_TRY(launch_fill_zero(P.xnorm, (size_t)P.ldn * 4, s));
+  HIP_TRY(launch_fill_zero(P.A, (size_t)P.ldz * 4, s));
+  HIP_TRY(launch_fill_zero(P.B, (size_t)P.ldz * 4, s));
+  if (P.n_obs > 0) HIP_TRY(launch_fill_zero(P.ob_acc, (size_t)(P.ldz + 1) * 8, s));
+  HIP_TRY(launch_fill_zero(P.sp_cnt, (size_t)P.Mp_pad * 4, s));
   return ENSF_OK;
 }
 
@@ -664,6 +673,35 @@ ensf_status analysis_impl(ensf_ctx* c, const std::vector<ensf_problem>& probs, h
   return mark_call_end(c, s);
 }
 
+ensf_status validate_options(const ensf_options& o) {
+  if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1 || o.lik_step < 0 ||
+      o.lik_step > 1 || o.wx_sparse < 0 || o.wx_sparse > 1)
+    return ENSF_EINVAL;
+  if (!(o.eps_alpha > 0.0 && o.eps_alpha < 1.0)) return ENSF_EINVAL;
+  if (!(o.spread_relax >= 0.0 && o.spread_relax <= 1.0)) return ENSF_EINVAL;
+  return ENSF_OK;
+}
+
+// Layout of run_in_workspace's buffer: the two device counters, the descriptor table, then
+// the problem's workspace, each 256-byte aligned.  A context-free plan with the built-in
+// tile heuristic (no tune table, no graph).
+constexpr size_t kCounterBytes = 256;
+
+struct WsLayout {
+  Plan plan;
+  Uploaded u;
+  size_t table = 0, total = 0;
+};
+
+ensf_status plan_in_workspace(ensf_ctx& tmp, const ensf_problem& p, WsLayout& L) {
+  const TileChoice tc = heuristic_tiles(p.n_members, p.n_particles);
+  ensf_status st = build_plan(&tmp, {p}, L.plan, &tc);
+  if (st != ENSF_OK) return st;
+  L.table = (size_t)round_up((int64_t)stage_plan(L.plan, nullptr, nullptr, L.u), kAlign);
+  L.total = kCounterBytes + L.table + L.plan.ws_needed;
+  return ENSF_OK;
+}
+
 // ----- tune cache: a flat JSON object {"key": [gram, wx, split_scale], ...}
 void load_tune_cache(ensf_ctx* c) {
   if (c->tune_path.empty()) return;
@@ -714,6 +752,53 @@ void save_tune_cache(ensf_ctx* c) {
 
 }  // namespace
 
+namespace ensf {
+
+size_t workspace_bytes(const ensf_options& o, const ensf_problem& p) {
+  if (validate_options(o) != ENSF_OK || validate(p) != ENSF_OK) return 0;
+  ensf_ctx tmp;
+  tmp.opt = o;
+  WsLayout L;
+  return plan_in_workspace(tmp, p, L) == ENSF_OK ? L.total : 0;
+}
+
+ensf_status run_in_workspace(const ensf_options& o, const ensf_problem& p, char* ws,
+                             size_t ws_bytes, unsigned long long* counters, hipStream_t s) {
+  ensf_status st = validate_options(o);
+  if (st == ENSF_OK) st = validate(p);
+  if (st != ENSF_OK) return st;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return ENSF_EINVAL;
+  clear_stale_hip_error();
+  ensf_ctx tmp;   // options and views only: owns no device or pinned memory
+  tmp.opt = o;
+  tmp.device = o.device;
+  WsLayout L;
+  st = plan_in_workspace(tmp, p, L);
+  if (st != ENSF_OK) return st;
+  if (L.total > ws_bytes) return ENSF_ESCRATCH;
+  char* tab = ws + kCounterBytes;
+  tmp.ws = tab + L.table;
+  tmp.ws_bytes = L.plan.ws_needed;
+  tmp.d_counters = counters ? counters : reinterpret_cast<unsigned long long*>(ws);
+  if (!counters) HIP_TRY(launch_fill_zero(ws, kCounterBytes, s));
+  const std::vector<ensf_problem> probs{p};
+  bind_plan(&tmp, probs, L.plan);
+  std::vector<char> host(L.table);
+  stage_plan(L.plan, host.data(), tab, L.u);
+  HIP_TRY(launch_put_bytes(tab, host.data(), host.size(), s));
+  if (L.plan.max_ldn * sizeof(double) > 64 * 1024)
+    HIP_TRY(set_softmax_smem_limit((size_t)L.plan.max_ldn * sizeof(double)));
+  const ProbDev& P = L.plan.desc[0];
+  st = prep_problem(&tmp, P, false, s);
+  if (st == ENSF_OK) st = enqueue_steps(&tmp, L.plan, L.u, s);
+  if (st != ENSF_OK) return st;
+  if (o.spread_relax > 0.0 && P.Mp > 1 && P.N > 1) HIP_TRY(launch_relax(P, o.spread_relax, s));
+  HIP_TRY(launch_store_post(P, s));
+  return ENSF_OK;
+}
+
+}  // namespace ensf
+
 extern "C" {
 
 void ensf_default_options(ensf_options* opt) {
@@ -735,11 +820,7 @@ ensf_status ensf_create(const ensf_options* opt, ensf_ctx** out) {
   ensf_options o;
   ensf_default_options(&o);
   if (opt) o = *opt;
-  if (o.precision < 0 || o.precision > 2 || o.obs_op < 0 || o.obs_op > 1 || o.lik_step < 0 ||
-      o.lik_step > 1 || o.wx_sparse < 0 || o.wx_sparse > 1)
-    return ENSF_EINVAL;
-  if (!(o.eps_alpha > 0.0 && o.eps_alpha < 1.0)) return ENSF_EINVAL;
-  if (!(o.spread_relax >= 0.0 && o.spread_relax <= 1.0)) return ENSF_EINVAL;
+  if (validate_options(o) != ENSF_OK) return ENSF_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ENSF_EHIP;
   if (o.device < 0 || o.device >= ndev) return ENSF_EINVAL;
@@ -998,6 +1079,7 @@ const char* ensf_status_string(ensf_status s) {
     case ENSF_EHIP: return "HIP runtime error";
     case ENSF_ENONFINITE: return "non-finite particle values";
     case ENSF_EUNSUPPORTED: return "unsupported";
+    case ENSF_ESCRATCH: return "problem exceeds the no-allocation scratch buffer";
   }
   return "unknown status";
 }

@@ -13,7 +13,9 @@ LIB_PATH = os.path.join(HERE, "libensf.so")
 # tile shapes measured by ensf_autotune on MI355X for the benchmark shapes
 DEFAULT_TUNE_CACHE = os.path.join(HERE, "tune_gfx950.json")
 
-ENSF_OK, ENSF_EINVAL, ENSF_ENOMEM, ENSF_EHIP, ENSF_ENONFINITE, ENSF_EUNSUPPORTED = range(6)
+(ENSF_OK, ENSF_EINVAL, ENSF_ENOMEM, ENSF_EHIP, ENSF_ENONFINITE, ENSF_EUNSUPPORTED,
+ ENSF_ESCRATCH) = range(7)
+NOALLOC_SCRATCH_BYTES = 64 << 20   # ENSF_NOALLOC_SCRATCH_BYTES
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "bf16": 2}
 OBS_OPS = {"arctan": 0, "linear": 1}
 LIK_STEPS = {"explicit": 0, "implicit": 1}
@@ -50,7 +52,8 @@ _LIB = None
 EXPORTS = ("ensf_default_options", "ensf_create", "ensf_analysis", "ensf_analysis_batched",
            "ensf_score", "ensf_rng_normal", "ensf_ensemble_stats", "ensf_sync_status",
            "ensf_autotune", "ensf_autotune_batched", "ensf_profile_phases", "ensf_phase_times",
-           "ensf_destroy", "ensf_status_string", "ensf_last_error_string")
+           "ensf_destroy", "ensf_status_string", "ensf_last_error_string",
+           "ensf_analysis_noalloc")
 
 
 def _lib():
@@ -78,6 +81,8 @@ def _lib():
         L.ensf_profile_phases.argtypes = [vp, i32]
         L.ensf_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.ensf_destroy.argtypes = [vp]
+        L.ensf_analysis_noalloc.argtypes = [ctypes.POINTER(ensf_options), vp, i32, i64, vp, i32,
+                                            vp, vp, i64, ctypes.c_float, i32, u64, u32, vp, vp]
         L.ensf_status_string.argtypes = [ctypes.c_int]
         L.ensf_status_string.restype = ctypes.c_char_p
         L.ensf_last_error_string.argtypes = []
@@ -133,16 +138,8 @@ def ensf_default_options():
 def ensf_create(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=0.0,
                 use_graph=True, device=0, tune_cache=DEFAULT_TUNE_CACHE, lik_step="explicit",
                 wx_sparse=False):
-    o = ensf_default_options()
-    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
-    o.eps_alpha = eps_alpha
-    o.spread_relax = spread_relax
-    o.use_graph = 1 if use_graph else 0
-    o.device = device
-    o.tune_cache = tune_cache.encode() if tune_cache else None
-    o.lik_step = LIK_STEPS[lik_step] if isinstance(lik_step, str) else int(lik_step)
-    o.wx_sparse = 1 if wx_sparse else 0
+    o = make_options(precision, obs_op, eps_alpha, spread_relax, use_graph, device, tune_cache,
+                     lik_step, wx_sparse)
     h = ctypes.c_void_p()
     _check(_lib().ensf_create(ctypes.byref(o), ctypes.byref(h)), "ensf_create")
     return h
@@ -157,6 +154,39 @@ def ensf_analysis(ctx, prior, post, obs_idx, obs_val, obs_sigma, n_steps, seed, 
                                 _ptr(post, torch.float32, "post"), post.shape[0], idx, val, m,
                                 float(obs_sigma), int(n_steps), int(seed), int(filter_id),
                                 _stream(stream)), "ensf_analysis")
+
+
+def make_options(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax=0.0,
+                 use_graph=True, device=0, tune_cache=None, lik_step="explicit",
+                 wx_sparse=False):
+    o = ensf_default_options()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
+    o.eps_alpha = eps_alpha
+    o.spread_relax = spread_relax
+    o.use_graph = 1 if use_graph else 0
+    o.device = device
+    o.tune_cache = tune_cache.encode() if tune_cache else None
+    o.lik_step = LIK_STEPS[lik_step] if isinstance(lik_step, str) else int(lik_step)
+    o.wx_sparse = 1 if wx_sparse else 0
+    return o
+
+
+def ensf_analysis_noalloc(prior, post, obs_idx, obs_val, obs_sigma, n_steps, seed, filter_id=0,
+                          counters=None, stream=None, **options):
+    """Context-free analysis in the library's static scratch buffer (no allocation).
+    counters: None or an int64 GPU tensor of 2 elements that the call adds to (non-finite
+    particle values, invalid observations).  options: as ensf_create."""
+    import torch
+    N, d = prior.shape
+    idx, val, m = _obs(obs_idx, obs_val)
+    o = make_options(**options)
+    _check(_lib().ensf_analysis_noalloc(ctypes.byref(o), _ptr(prior, torch.float32, "prior"), N,
+                                        d, _ptr(post, torch.float32, "post"), post.shape[0], idx,
+                                        val, m, float(obs_sigma), int(n_steps), int(seed),
+                                        int(filter_id),
+                                        _ptr(counters, torch.int64, "counters"),
+                                        _stream(stream)), "ensf_analysis_noalloc")
 
 
 def make_problem(prior, post, obs_idx, obs_val, obs_sigma, n_steps, seed, filter_id=0):
