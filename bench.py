@@ -103,6 +103,60 @@ def run_cycle_bench(a):
     print(json.dumps(line), flush=True)
 
 
+def vit_training_flops(layers, tokens, embed, mlp_hidden, patch_dim, batch):
+    """Matrix-product flops of one ViT training step (2 per multiply-add): forward, and the
+    weight gradients of every linear layer plus the input gradients of all but the patch
+    embedding (3x the forward for the blocks and the head, 2x for the embedding); attention's
+    q k^T and P v per head, forward (2) and backward (4)."""
+    D, F, P, T = embed, mlp_hidden, patch_dim, tokens
+    body = layers * (3 * D * D + D * D + 2 * D * F) + D * P
+    per_token = 3 * 2 * body + 2 * 2 * P * D
+    attn = 3 * layers * 2 * 2 * T * T * D
+    return batch * (T * per_token + attn)
+
+
+def run_vit_bench(a):
+    """Training throughput of the Table II 64^2 ViT surrogate (patch 4, 12 layers, 8 heads,
+    embed 1024, MLP ratio 4) on synthetic 2 x 64 x 64 states, as matrix-product TFLOP/s."""
+    import torch
+
+    from paper_2407_12168_amd import vit
+    dev = torch.device("cuda:0")
+    B = a.vit_batch
+    g = torch.Generator(device="cpu").manual_seed(2407)
+    x = torch.randn((B, 2, 64, 64), generator=g).to(dev)
+    t = (x + 0.1 * torch.randn(x.shape, generator=g).to(dev)).contiguous()
+    m = vit.ViT(channels=2, height=64, width=64, patch=4, layers=12, heads=8, embed=1024,
+                mlp_hidden=4096, max_batch=B, seed=1)
+    h = m.handle
+    for _ in range(a.warmup):
+        vit.ensf_vit_train_step(h, x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        vit.ensf_vit_train_step(h, x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / a.steps * 1e3
+    loss = vit.ensf_vit_train_step(h, x, t, 1e-4)
+    n_params = vit.ensf_vit_num_params(h)
+    m.destroy()
+    flops = vit_training_flops(12, 256, 1024, 4096, 32, B)
+    tf = flops / (ms * 1e-3) / 1e12
+    line = {
+        "metric": "ViT surrogate training TFLOP/s (matrix products)", "value": tf,
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"ViT 64x64 input, patch 4, 12 layers, 8 heads, embed 1024, "
+                               f"MLP 4096 ({n_params} parameters), batch {B}, forward + "
+                               f"backward + Adam", "batch": B, "params": n_params},
+        "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None},
+        "flops_per_step": flops, "final_loss": loss,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_form(probs, precision, steps, warmup, dev, lik_step="explicit", wx_sparse=False):
     """Times ensf_analysis (one problem) or ensf_analysis_batched (several) on `probs`."""
     import torch
@@ -237,12 +291,18 @@ def main():
                     help="pseudo-steps of the oracle's timed sample (default: all, except "
                          "10 at d = 131072)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--vit", action="store_true",
+                    help="time the Table II 64x64 ViT surrogate's training step instead")
+    ap.add_argument("--vit-batch", type=int, default=32)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: runs on one GPU only (the analysis would shard over particles or "
               "filters; there is no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
 
+    if a.vit:
+        run_vit_bench(a)
+        return
     if a.config == 5:
         run_cycle_bench(a)
         return

@@ -1,0 +1,590 @@
+// HIP kernels of the transformer forecast surrogate (Sec. III-B: a ViT backbone whose cost is
+// dominated by its matrix products) for CDNA4 (gfx950).
+//
+// Every matrix product, forward and backward, is one form: C = alpha A B^T with both operands
+// BF16 and contiguous along the contraction (k), on v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation, batched over (image, head) for attention.  The operands that a backward
+// product needs in the other orientation are written transposed by the kernel that produces
+// them (GEMM epilogues, LayerNorm, softmax, patch extraction), so no product reads a strided
+// operand.  Everything elementwise (bias, residual add, GELU and its derivative, LayerNorm,
+// softmax, the loss) is fused into those producers.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mfma_tile.h"
+#include "vit_internal.h"
+
+namespace ensf {
+namespace vit {
+
+namespace {
+
+constexpr int kRows = 32;   // rows per workgroup of the row-wise kernels (4 waves x 8)
+
+__device__ __forceinline__ uint16_t to_bf16(float v) {
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+__device__ __forceinline__ float gelu_f(float v) {
+  return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad_f(float u) {
+  const float cdf = 0.5f * (1.0f + erff(u * 0.70710678118654752f));
+  return cdf + u * 0.39894228040143268f * expf(-0.5f * u * u);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Writes a kRows x cols BF16 tile held in LDS (row stride cols + 2, which spreads the column
+// reads of the two rows a thread packs over distinct banks) transposed: dst[c * ld + r] for
+// r < kRows, two rows per 4-byte store, 16 threads per destination row (64 contiguous bytes).
+__device__ __forceinline__ void store_tile_transposed(const uint16_t* tile, int cols,
+                                                      uint16_t* dst, int64_t ld) {
+  const int lds = cols + 2;
+  for (int i = threadIdx.x; i < cols * (kRows / 2); i += blockDim.x) {
+    const int c = i / (kRows / 2), pr = i % (kRows / 2);
+    const uint32_t w = (uint32_t)tile[(2 * pr) * lds + c] |
+                       ((uint32_t)tile[(2 * pr + 1) * lds + c] << 16);
+    *reinterpret_cast<uint32_t*>(dst + (int64_t)c * ld + 2 * pr) = w;
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------------
+// C = alpha A B^T with the fused epilogue of VGemm.
+
+template <int WGM, int WGN, int TM, int TN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_vgemm(VGemm g) {
+  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32, BK = 32;
+  using S = TileSmem<kBF16, BM, BN, BK, false>;
+  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
+
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = tile % g.tiles_n, tm = tile / g.tiles_n;
+  const int z = blockIdx.y, zb = z / g.nh, zh = z - zb * g.nh;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+
+  f32x16_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  const uint16_t* pa = g.A.p + zb * g.A.sb + zh * g.A.sh;
+  const uint16_t* pb = g.B.p + zb * g.B.sb + zh * g.B.sh;
+  Bf16KmajLoad<BM, NT, false, BK> la;
+  Bf16KmajLoad<BN, NT, false, BK> lb;
+  la.init(pa, pa, g.A.ld, m0);
+  lb.init(pb, pb, g.B.ld, n0);
+  tile_k_loop<kBF16, WGM, WGN, TM, TN, BK, PP, false>(
+      smem, 0, g.K,
+      [&](int64_t kb) {
+        la.load(kb);
+        lb.load(kb);
+      },
+      [&](char* st) {
+        uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
+        uint16_t* sAl = sAh + BM * S::LDH;
+        uint16_t* sBh = sAl + BM * S::LDH;
+        la.store(sAh, sAl, S::LDH);
+        lb.store(sBh, sBh + BN * S::LDH, S::LDH);
+      },
+      acc);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* f32 = g.f32 ? g.f32 + zb * g.sb_f32 + zh * g.sh_f32 : nullptr;
+  uint16_t* b16 = g.b16 ? g.b16 + zb * g.sb_b16 + zh * g.sh_b16 : nullptr;
+  uint16_t* b16t = g.b16t ? g.b16t + zb * g.sb_t + zh * g.sh_t : nullptr;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) {
+    const int64_t n = n0 + wn * TN * 32 + b * 32 + (lane & 31);
+    const float bias = g.bias ? g.bias[n] : 0.0f;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const int64_t mb = m0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+        uint16_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t m = mb + j;
+          float v = g.alpha * acc[a][b][gq * 4 + j] + bias;
+          if (g.add) v += g.add[(g.add_rows ? m % g.add_rows : m) * g.ld_add + n];
+          if (f32) f32[m * g.ld_f32 + n] = v;
+          if (g.act == 1)
+            v = gelu_f(v);
+          else if (g.act == 2)
+            v *= gelu_grad_f(g.gin[m * g.ld_gin + n]);
+          h[j] = to_bf16(v);
+          if (b16) b16[m * g.ld_b16 + n] = h[j];
+        }
+        if (b16t) {
+          const uint2 w = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                     (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+          *reinterpret_cast<uint2*>(b16t + n * g.ld_t + mb) = w;
+        }
+      }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// LayerNorm
+
+__global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const float* gam,
+                                                const float* bet, uint16_t* y, uint16_t* yt,
+                                                int64_t ld_t, float* mean, float* rstd) {
+  extern __shared__ uint16_t tile[];   // kRows x (D + 2)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kRows;
+  for (int rr = wave; rr < kRows; rr += 4) {
+    const int64_t r = r0 + rr;
+    const float* xr = x + r * D;
+    float s = 0.0f;
+    for (int d = lane; d < D; d += 64) s += xr[d];
+    const float mu = wave_sum(s) / (float)D;
+    float q = 0.0f;
+    for (int d = lane; d < D; d += 64) {
+      const float c = xr[d] - mu;
+      q += c * c;
+    }
+    const float rs = 1.0f / sqrtf(wave_sum(q) / (float)D + 1e-5f);
+    for (int d = lane; d < D; d += 64) {
+      const uint16_t b = to_bf16((xr[d] - mu) * rs * gam[d] + bet[d]);
+      y[r * D + d] = b;
+      if (yt) tile[rr * (D + 2) + d] = b;
+    }
+    if (lane == 0) {
+      mean[r] = mu;
+      rstd[r] = rs;
+    }
+  }
+  if (!yt) return;
+  __syncthreads();
+  store_tile_transposed(tile, D, yt + r0, ld_t);
+}
+
+// dres += LayerNorm backward of dy; BF16 copies of the updated dres; per-wave partial sums
+// of dy * xhat and dy over its 8 rows.  D <= 2048, D % 64 == 0.
+__global__ __launch_bounds__(256) void k_ln_bwd(const float* dy, const float* x,
+                                                const float* mean, const float* rstd,
+                                                const float* gam, int D, float* dres,
+                                                uint16_t* res16, uint16_t* res16t,
+                                                int64_t ld_t, float* pg, float* pb) {
+  extern __shared__ uint16_t tile[];   // kRows x (D + 2)
+  constexpr int kMaxJ = 2048 / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kRows;
+  float sg[kMaxJ], sb[kMaxJ];
+#pragma unroll
+  for (int j = 0; j < kMaxJ; ++j) sg[j] = sb[j] = 0.0f;
+  for (int rr = wave * 8; rr < wave * 8 + 8; ++rr) {
+    const int64_t r = r0 + rr;
+    const float mu = mean[r], rs = rstd[r];
+    float dv[kMaxJ], xh[kMaxJ];
+    float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int d = j * 64 + lane;
+      if (d < D) {
+        const float g = dy[r * D + d];
+        xh[j] = (x[r * D + d] - mu) * rs;
+        dv[j] = g * gam[d];
+        s1 += dv[j];
+        s2 += dv[j] * xh[j];
+        sg[j] += g * xh[j];
+        sb[j] += g;
+      }
+    }
+    s1 = wave_sum(s1) / (float)D;
+    s2 = wave_sum(s2) / (float)D;
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int d = j * 64 + lane;
+      if (d < D) {
+        float* o = dres + r * D + d;
+        const float v = *o + rs * (dv[j] - s1 - xh[j] * s2);
+        *o = v;
+        const uint16_t b = to_bf16(v);
+        if (res16) res16[r * D + d] = b;
+        if (res16t) tile[rr * (D + 2) + d] = b;
+      }
+    }
+  }
+  const int64_t prow = (r0 >> 3) + wave;
+#pragma unroll
+  for (int j = 0; j < kMaxJ; ++j) {
+    const int d = j * 64 + lane;
+    if (d < D) {
+      pg[prow * D + d] = sg[j];
+      pb[prow * D + d] = sb[j];
+    }
+  }
+  if (!res16t) return;
+  __syncthreads();
+  store_tile_transposed(tile, D, res16t + r0, ld_t);
+}
+
+// ----------------------------------------------------------------------------------------
+// reductions
+
+__global__ __launch_bounds__(256) void k_sum_rows(const float* src, int64_t r, int64_t cols,
+                                                  float* out, int accumulate) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < r; ++i) s += src[i * cols + c];
+  out[c] = accumulate ? (float)(out[c] + s) : (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_rowsum_bf16(const uint16_t* src, int64_t rows,
+                                                     int64_t cols, int64_t ld, float* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  double s = 0.0;
+  for (int64_t c = lane; c < cols; c += 64) s += from_bf16(src[row * ld + c]);
+  s = wave_sum_d(s);
+  if (lane == 0) out[row] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_batches(const float* src, int B, int T, int D,
+                                                     float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)T * D) return;
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += src[(int64_t)b * T * D + i];
+  out[i] = (float)s;
+}
+
+// ----------------------------------------------------------------------------------------
+// attention rows
+
+__global__ __launch_bounds__(256) void k_attn_softmax(const float* S, int T, uint16_t* P,
+                                                      uint16_t* Pt) {
+  extern __shared__ uint16_t tile[];   // kRows x (T + 2)
+  constexpr int kMaxJ = 1024 / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t z = blockIdx.y;
+  const int64_t q0 = (int64_t)blockIdx.x * kRows;
+  const float* Sz = S + z * T * T;
+  for (int rr = wave; rr < kRows; rr += 4) {
+    const float* row = Sz + (q0 + rr) * T;
+    float v[kMaxJ];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (j * 64 + lane < T) {
+        v[j] = row[j * 64 + lane];
+        mx = fmaxf(mx, v[j]);
+      }
+    mx = wave_max(mx);
+    float sum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (j * 64 + lane < T) {
+        v[j] = expf(v[j] - mx);
+        sum += v[j];
+      }
+    const float inv = 1.0f / wave_sum(sum);
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (j * 64 + lane < T) {
+        const uint16_t b = to_bf16(v[j] * inv);
+        P[z * T * T + (q0 + rr) * T + j * 64 + lane] = b;
+        tile[rr * (T + 2) + j * 64 + lane] = b;
+      }
+  }
+  __syncthreads();
+  store_tile_transposed(tile, T, Pt + z * T * T + q0, T);
+}
+
+__global__ __launch_bounds__(256) void k_attn_ds(const uint16_t* P, const float* dP, int T,
+                                                 float scale, uint16_t* dS, uint16_t* dSt) {
+  extern __shared__ uint16_t tile[];   // kRows x (T + 2)
+  constexpr int kMaxJ = 1024 / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t z = blockIdx.y;
+  const int64_t q0 = (int64_t)blockIdx.x * kRows;
+  for (int rr = wave; rr < kRows; rr += 4) {
+    const int64_t o = z * T * T + (q0 + rr) * T;
+    float p[kMaxJ], g[kMaxJ];
+    float dot = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (j * 64 + lane < T) {
+        p[j] = from_bf16(P[o + j * 64 + lane]);
+        g[j] = dP[o + j * 64 + lane];
+        dot += p[j] * g[j];
+      }
+    dot = wave_sum(dot);
+#pragma unroll
+    for (int j = 0; j < kMaxJ; ++j)
+      if (j * 64 + lane < T) {
+        const uint16_t b = to_bf16(scale * p[j] * (g[j] - dot));
+        dS[o + j * 64 + lane] = b;
+        tile[rr * (T + 2) + j * 64 + lane] = b;
+      }
+  }
+  __syncthreads();
+  store_tile_transposed(tile, T, dSt + z * T * T + q0, T);
+}
+
+// ----------------------------------------------------------------------------------------
+// patches, head output and loss
+
+struct ImgGeom {
+  int B, C, H, W, p;
+  __device__ __forceinline__ int tokens() const { return (H / p) * (W / p); }
+  __device__ __forceinline__ int pdim() const { return C * p * p; }
+  // image element i = ((b C + c) H + y) W + x -> (token row, patch column)
+  __device__ __forceinline__ void map(int64_t i, int64_t& tok, int& e) const {
+    const int x = (int)(i % W);
+    const int y = (int)((i / W) % H);
+    const int c = (int)((i / ((int64_t)W * H)) % C);
+    const int64_t b = i / ((int64_t)W * H * C);
+    tok = b * tokens() + (int64_t)(y / p) * (W / p) + x / p;
+    e = c * p * p + (y % p) * p + x % p;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_patchify(const float* x, ImgGeom G, uint16_t* pt,
+                                                  uint16_t* ptt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)G.B * G.C * G.H * G.W;
+  if (i >= n) return;
+  int64_t tok;
+  int e;
+  G.map(i, tok, e);
+  const uint16_t b = to_bf16(x[i]);
+  const int64_t rows = (int64_t)G.B * G.tokens();
+  pt[tok * G.pdim() + e] = b;
+  ptt[(int64_t)e * rows + tok] = b;
+}
+
+__global__ __launch_bounds__(256) void k_head_out(const float* tok, const float* x,
+                                                  const float* target, float* y, ImgGeom G,
+                                                  uint16_t* dy, uint16_t* dyt, double* lossp) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)G.B * G.C * G.H * G.W;
+  double r2 = 0.0;
+  if (i < n) {
+    int64_t t;
+    int e;
+    G.map(i, t, e);
+    const float v = x[i] + tok[t * G.pdim() + e];
+    if (y) y[i] = v;
+    if (target) {
+      const float r = v - target[i];
+      r2 = (double)r * (double)r;
+      const uint16_t b = to_bf16(2.0f * r / (float)n);
+      const int64_t rows = (int64_t)G.B * G.tokens();
+      dy[t * G.pdim() + e] = b;
+      dyt[(int64_t)e * rows + t] = b;
+    }
+  }
+  if (!target) return;
+  r2 = wave_sum_d(r2);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) lossp[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_loss_final(const double* lossp, int n, double numel, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += lossp[i];
+  *out = s / numel;
+}
+
+// ----------------------------------------------------------------------------------------
+// parameters
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* w, int rows, int cols,
+                                                 uint16_t* w16, uint16_t* w16t) {
+  __shared__ uint16_t t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int rr = r0 + r, cc = c0 + tx;
+    if (rr < rows && cc < cols) {
+      const uint16_t b = to_bf16(w[(int64_t)rr * cols + cc]);
+      w16[(int64_t)rr * cols + cc] = b;
+      t[r][tx] = b;
+    }
+  }
+  __syncthreads();
+  for (int c = ty; c < 32; c += 8) {
+    const int cc = c0 + c, rr = r0 + tx;
+    if (rr < rows && cc < cols) w16t[(int64_t)cc * rows + rr] = t[tx][c];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* w, const float* g, float* m, float* v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ----------------------------------------------------------------------------------------
+// host launchers
+
+namespace {
+inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+}
+
+hipError_t launch_vgemm(const VGemm& g0, int batch, hipStream_t s) {
+  VGemm g = g0;
+  if (g.K % 32 != 0 || g.K <= 0) return hipErrorInvalidValue;
+  auto go = [&](auto kern, int bm, int bn, int threads) {
+    g.tiles_n = g.N / bn;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((g.M / bm) * (g.N / bn)), (unsigned)batch),
+                       dim3(threads), 0, s, g);
+    return hipGetLastError();
+  };
+  if (g.M % 128 == 0 && g.N % 128 == 0) return go(k_vgemm<2, 2, 2, 2>, 128, 128, 256);
+  if (g.M % 64 == 0 && g.N % 64 == 0) return go(k_vgemm<2, 2, 1, 1>, 64, 64, 256);
+  if (g.M % 32 == 0 && g.N % 32 == 0) return go(k_vgemm<1, 1, 1, 1>, 32, 32, 64);
+  return hipErrorInvalidValue;
+}
+
+hipError_t set_vit_smem_limit(int D, int T) {
+  const int ln = kRows * (D + 2) * 2, rows = kRows * (T + 2) * 2;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f, int bytes) {
+    if (e == hipSuccess && bytes > 64 * 1024)
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+  set(reinterpret_cast<const void*>(k_ln_fwd), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd), ln);
+  set(reinterpret_cast<const void*>(k_attn_softmax), rows);
+  set(reinterpret_cast<const void*>(k_attn_ds), rows);
+  return e;
+}
+
+hipError_t launch_ln_fwd(const float* x, int64_t rows, int D, const float* gamma,
+                         const float* beta, uint16_t* y, uint16_t* yt, int64_t ld_t,
+                         float* mean, float* rstd, hipStream_t s) {
+  if (rows % kRows != 0 || D % 64 != 0 || D > 2048) return hipErrorInvalidValue;
+  const size_t shm = yt ? (size_t)kRows * (D + 2) * 2 : 0;
+  hipLaunchKernelGGL(k_ln_fwd, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, x, D, gamma,
+                     beta, y, yt, ld_t, mean, rstd);
+  return hipGetLastError();
+}
+
+hipError_t launch_ln_bwd(const float* dy, const float* x, const float* mean, const float* rstd,
+                         const float* gamma, int64_t rows, int D, float* dres,
+                         uint16_t* res16, uint16_t* res16t, int64_t ld_t, float* pg,
+                         float* pb, hipStream_t s) {
+  if (rows % kRows != 0 || D % 64 != 0 || D > 2048) return hipErrorInvalidValue;
+  const size_t shm = res16t ? (size_t)kRows * (D + 2) * 2 : 0;
+  hipLaunchKernelGGL(k_ln_bwd, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, dy, x, mean,
+                     rstd, gamma, D, dres, res16, res16t, ld_t, pg, pb);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out, bool accumulate,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_rows, dim3(blocks(cols, 256)), dim3(256), 0, s, src, r, cols, out,
+                     accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsum_bf16(const uint16_t* src, int64_t rows, int64_t cols, int64_t ld,
+                              float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowsum_bf16, dim3(blocks(rows, 4)), dim3(256), 0, s, src, rows, cols, ld,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_batches(const float* src, int B, int T, int D, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_batches, dim3(blocks((int64_t)T * D, 256)), dim3(256), 0, s, src, B,
+                     T, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_softmax(const float* S, int64_t Z, int T, uint16_t* P, uint16_t* Pt,
+                               hipStream_t s) {
+  if (T % 64 != 0 || T > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_attn_softmax, dim3((unsigned)(T / kRows), (unsigned)Z), dim3(256),
+                     (size_t)kRows * (T + 2) * 2, s, S, T, P, Pt);
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_ds(const uint16_t* P, const float* dP, int64_t Z, int T, float scale,
+                          uint16_t* dS, uint16_t* dSt, hipStream_t s) {
+  if (T % 64 != 0 || T > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_attn_ds, dim3((unsigned)(T / kRows), (unsigned)Z), dim3(256),
+                     (size_t)kRows * (T + 2) * 2, s, P, dP, T, scale, dS, dSt);
+  return hipGetLastError();
+}
+
+hipError_t launch_patchify(const float* x, int B, int C, int H, int W, int p, uint16_t* pt,
+                           uint16_t* ptt, hipStream_t s) {
+  const ImgGeom G{B, C, H, W, p};
+  const int64_t n = (int64_t)B * C * H * W;
+  hipLaunchKernelGGL(k_patchify, dim3(blocks(n, 256)), dim3(256), 0, s, x, G, pt, ptt);
+  return hipGetLastError();
+}
+
+int loss_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+hipError_t launch_head_out(const float* tok, const float* x, const float* target, float* y,
+                           int B, int C, int H, int W, int p, uint16_t* dy, uint16_t* dyt,
+                           double* lossp, hipStream_t s) {
+  const ImgGeom G{B, C, H, W, p};
+  const int64_t n = (int64_t)B * C * H * W;
+  hipLaunchKernelGGL(k_head_out, dim3((unsigned)loss_blocks(n)), dim3(256), 0, s, tok, x, target,
+                     y, G, dy, dyt, lossp);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_final(const double* lossp, int n, double numel, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, lossp, n, numel, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* w, int rows, int cols, uint16_t* w16, uint16_t* w16t,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks(cols, 32), blocks(rows, 32)), dim3(256), 0, s, w,
+                     rows, cols, w16, w16t);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(blocks(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, beta1,
+                     beta2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+}  // namespace vit
+}  // namespace ensf

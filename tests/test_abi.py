@@ -24,7 +24,9 @@ def declared_entry_points():
 
 def test_headers_declare_the_binding_names():
     from paper_2407_12168_amd import sqg, surrogate
-    assert declared_entry_points() == sorted(ensf.EXPORTS + surrogate.EXPORTS + sqg.EXPORTS)
+    from paper_2407_12168_amd import vit
+    assert declared_entry_points() == sorted(ensf.EXPORTS + surrogate.EXPORTS + sqg.EXPORTS +
+                                             vit.EXPORTS)
 
 
 @pytest.fixture(scope="module")
