@@ -446,19 +446,13 @@ __device__ __forceinline__ WxEpi make_wx_epi(const ProbDev& P, int step, int64_t
   return E;
 }
 
-// One accumulator quad of a lane: block (a, b), register group gq, i.e. xhat for four
-// consecutive components e..e+3 of particle i (one Philox counter).  SCORE writes the
-// posterior score; otherwise the particle components are advanced one step in place.
-template <int WGN, int TM, int TN, bool SCORE, int OP, bool IMPLICIT>
-__device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc)[TM][TN], int a,
-                                            int b, int gq, unsigned int& bad) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
-  const int64_t i = E.i0 + wn * TN * 32 + b * 32 + (lane & 31);
-  const int64_t e = E.e0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+// xhat for the four consecutive components e..e+3 of particle i (one Philox counter).  SCORE
+// writes the posterior score; otherwise the particle components are advanced one step in
+// place.
+template <bool SCORE, int OP, bool IMPLICIT>
+__device__ __forceinline__ void wx_epi_elems(const WxEpi& E, int64_t i, int64_t e, f32x4 xh,
+                                             unsigned int& bad) {
   if (i >= E.Mp || e >= E.d) return;
-  const float xh0 = acc[a][b][gq * 4 + 0], xh1 = acc[a][b][gq * 4 + 1];
-  const float xh2 = acc[a][b][gq * 4 + 2], xh3 = acc[a][b][gq * 4 + 3];
   f32x4* zp = reinterpret_cast<f32x4*>(E.Z + i * E.ldz + e);
   const f32x4 z = gload(zp);
   const f32x4 av = gload(reinterpret_cast<const f32x4*>(E.A + e));
@@ -466,10 +460,10 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
   const int64_t rem = E.d - e;
   if constexpr (SCORE) {
     float* so = E.score_out + i * E.d + e;
-    so[0] = posterior_score<OP>(z.x, xh0, av.x, bv.x, E.sc);
-    if (rem > 1) so[1] = posterior_score<OP>(z.y, xh1, av.y, bv.y, E.sc);
-    if (rem > 2) so[2] = posterior_score<OP>(z.z, xh2, av.z, bv.z, E.sc);
-    if (rem > 3) so[3] = posterior_score<OP>(z.w, xh3, av.w, bv.w, E.sc);
+    so[0] = posterior_score<OP>(z.x, xh.x, av.x, bv.x, E.sc);
+    if (rem > 1) so[1] = posterior_score<OP>(z.y, xh.y, av.y, bv.y, E.sc);
+    if (rem > 2) so[2] = posterior_score<OP>(z.z, xh.z, av.z, bv.z, E.sc);
+    if (rem > 3) so[3] = posterior_score<OP>(z.w, xh.w, av.w, bv.w, E.sc);
   } else {
     const Words4 w =
         philox4x32_10((uint32_t)(e >> 2), (uint32_t)i, (uint32_t)E.step, E.filt, E.k0, E.k1);
@@ -477,10 +471,10 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
     box_muller(w.w0, w.w1, n0, n1);
     box_muller(w.w2, w.w3, n2, n3);
     f32x4 zn;
-    zn.x = update_step<OP, IMPLICIT>(z.x, xh0, av.x, bv.x, n0, E.sc);
-    zn.y = update_step<OP, IMPLICIT>(z.y, xh1, av.y, bv.y, n1, E.sc);
-    zn.z = update_step<OP, IMPLICIT>(z.z, xh2, av.z, bv.z, n2, E.sc);
-    zn.w = update_step<OP, IMPLICIT>(z.w, xh3, av.w, bv.w, n3, E.sc);
+    zn.x = update_step<OP, IMPLICIT>(z.x, xh.x, av.x, bv.x, n0, E.sc);
+    zn.y = update_step<OP, IMPLICIT>(z.y, xh.y, av.y, bv.y, n1, E.sc);
+    zn.z = update_step<OP, IMPLICIT>(z.z, xh.z, av.z, bv.z, n2, E.sc);
+    zn.w = update_step<OP, IMPLICIT>(z.w, xh.w, av.w, bv.w, n3, E.sc);
     if (rem < 4) {  // ragged tail: keep the padding at zero
       zn.w = 0.0f;
       if (rem < 3) zn.z = 0.0f;
@@ -492,13 +486,68 @@ __device__ __forceinline__ void wx_epi_quad(const WxEpi& E, const f32x16_t (&acc
   }
 }
 
+// Orders a wave's LDS accesses before the ones that follow, for data exchanged between its
+// own lanes: no code motion across it (fence, wave barrier) and the wave's outstanding LDS
+// operations complete first (s_waitcnt lgkmcnt(0)).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The epilogue of a W.X tile.  In the accumulator layout a lane holds, per 32 x 32 block, the
+// component quads Q = 2 gq + lane / 32 of particle lane % 32, so a store instruction would
+// write 32-byte pieces of 32 particle rows.  Each block is therefore passed through a
+// wave-private 4 KB LDS region ([particle][component], 16-byte quads XOR-permuted by the
+// particle row) and read back with lane l on particle row 8 r + l / 8 and quad l % 8: eight
+// consecutive lanes then cover one 128-byte line of a particle row, so every Z, A and B access
+// of the epilogue is a whole line.  The per-element arithmetic is unchanged.
+template <int WGN, int TM, int TN, bool SCORE, int OP, bool IMPLICIT>
+__device__ __forceinline__ void wx_epilogue(const WxEpi& E, const f32x16_t (&acc)[TM][TN],
+                                            float* stage, unsigned int& bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* ws = stage + wave * 1024;
+  const int pw = lane & 31, q = lane & 7;
+#pragma unroll
+  for (int b = 0; b < TN; ++b)
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const int Q = 2 * gq + (lane >> 5);
+        *reinterpret_cast<f32x4*>(ws + pw * 32 + ((Q ^ (pw & 7)) << 2)) =
+            f32x4{acc[a][b][gq * 4 + 0], acc[a][b][gq * 4 + 1], acc[a][b][gq * 4 + 2],
+                  acc[a][b][gq * 4 + 3]};
+      }
+      // the wave reads what its other lanes wrote: order the LDS accesses within the wave
+      wave_lds_sync();
+      f32x4 xq[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pr = r * 8 + (lane >> 3);
+        xq[r] = *reinterpret_cast<const f32x4*>(ws + pr * 32 + ((q ^ (pr & 7)) << 2));
+      }
+      wave_lds_sync();
+      const int64_t e = E.e0 + wm * TM * 32 + a * 32 + 4 * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = E.i0 + wn * TN * 32 + b * 32 + r * 8 + (lane >> 3);
+        wx_epi_elems<SCORE, OP, IMPLICIT>(E, i, e, xq[r], bad);
+      }
+    }
+}
+
 template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE, bool SP = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
                                                        unsigned long long* nonfinite) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
   using S = TileSmem<PREC, BE, BP, BK, true>;
   constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
-  __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
+  // the epilogue stages one 32 x 32 FP32 block per wave through the operand buffer
+  constexpr int kStage = NT / 64 * 4096;
+  constexpr int kSmem = PP ? 2 * S::kBytes : S::kBytes;
+  __shared__ __attribute__((aligned(16))) char smem[kSmem > kStage ? kSmem : kStage];
 
   const int tile = xcd_remap(blockIdx.x, g.total);
   const int f = find_problem(g.pre, g.np, tile);
@@ -575,17 +624,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
 
   const WxEpi E = make_wx_epi(P, step, i0, e0, true);
   unsigned int bad = 0;
+  __syncthreads();   // every wave is done with the operand tiles before the staging reuses them
+  float* stage = reinterpret_cast<float*>(smem);
   // one specialised epilogue per observation operator and time-stepping variant (uniform)
   auto epilogue = [&](auto op_tag, auto impl_tag) {
     constexpr int OP = decltype(op_tag)::value;
     constexpr bool IMPL = decltype(impl_tag)::value;
-#pragma unroll
-    for (int b = 0; b < TN; ++b)
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int gq = 0; gq < 4; ++gq)
-          wx_epi_quad<WGN, TM, TN, SCORE, OP, IMPL>(E, acc, a, b, gq, bad);
+    wx_epilogue<WGN, TM, TN, SCORE, OP, IMPL>(E, acc, stage, bad);
   };
   using ArcT = std::integral_constant<int, kArctan>;
   using LinT = std::integral_constant<int, kLinear>;
