@@ -199,10 +199,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
         },
         [&](char* st) {
           uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
-          uint16_t* sAl = sAh + BM * S::LDH;
-          uint16_t* sBh = sAl + BM * S::LDH;
-          la.template store_split<LO>(sAh, sAl, S::LDH);
-          lb.store(sBh, sBh + BN * S::LDH, S::LDH);
+          la.template store_split<LO>(sAh, sAh + S::kALo, S::LDH);
+          lb.store(sAh + S::kBHi, sAh + S::kBLo, S::LDH);
         },
         acc);
   }
@@ -614,10 +612,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
         },
         [&](char* st) {
           uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
-          uint16_t* sAl = sAh + BE * S::LDH;
-          uint16_t* sBh = sAl + BE * S::LDH;
-          la.store(sAh, sAl, S::LDH);
-          lb.store(sBh, sBh + BP * S::LDH, S::LDH);
+          la.store(sAh, sAh + S::kALo, S::LDH);
+          lb.store(sAh + S::kBHi, sAh + S::kBLo, S::LDH);
         },
         acc);
   }

@@ -41,7 +41,12 @@ struct TileSmem {
   static constexpr int LDH = BK;                            // row-major rows (elements)
   static constexpr int kAFloats = AK ? BK * LDF_A : BM * BK;
   static constexpr int kFp32Bytes = (kAFloats + BN * BK) * 4;
-  static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * 2;
+  // BF16 tiles: A hi, then (split form only) A lo, then B hi, B lo; element offsets
+  static constexpr int kLo = PREC == kBF16X3 ? 1 : 0;
+  static constexpr int kALo = BM * LDH;
+  static constexpr int kBHi = (1 + kLo) * BM * LDH;
+  static constexpr int kBLo = kBHi + BN * LDH;
+  static constexpr int kBf16Bytes = (BM + BN) * LDH * 2 * (1 + kLo);
   static constexpr int kBytes = PREC == kFP32 ? kFp32Bytes : kBf16Bytes;
 };
 
@@ -108,9 +113,9 @@ __device__ __forceinline__ void mfma_block_compute(const char* smem, f32x16_t (&
     }
   } else {
     const uint16_t* sAh = reinterpret_cast<const uint16_t*>(smem);
-    const uint16_t* sAl = sAh + BM * S::LDH;
-    const uint16_t* sBh = sAl + BM * S::LDH;
-    const uint16_t* sBl = sBh + BN * S::LDH;
+    const uint16_t* sAl = sAh + S::kALo;
+    const uint16_t* sBh = sAh + S::kBHi;
+    const uint16_t* sBl = sAh + S::kBLo;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];

@@ -16,6 +16,8 @@ using namespace ensf::vit;
 
 namespace {
 
+constexpr int kMaxSplits = 8;
+
 struct Lin {
   int64_t w, b;      // offsets of weight (out x in) and bias (out) in the flat parameters
   int out, in;
@@ -68,6 +70,9 @@ struct ensf_vit {
   uint16_t *dS16 = nullptr, *dSt16 = nullptr;
   uint16_t *dy16 = nullptr, *dyt16 = nullptr;
   float *pg = nullptr, *pb = nullptr;
+  float* kpart = nullptr;     // split-K partial products of the weight gradients
+  size_t kpart_floats = 0;
+  double* rtmp = nullptr;     // group sums of the LayerNorm parameter gradients
   double *lossp = nullptr, *loss = nullptr;
 };
 
@@ -169,6 +174,11 @@ hipError_t allocate(ensf_vit* v) {
   A(&v->dS16, Z * TT); A(&v->dSt16, Z * TT);
   A(&v->dy16, Ta * P); A(&v->dyt16, Ta * P);
   A(&v->pg, Ta / 8 * D); A(&v->pb, Ta / 8 * D);
+  size_t maxw = 0;
+  for (const Lin& l : v->lins) maxw = std::max(maxw, (size_t)l.out * l.in);
+  v->kpart_floats = kMaxSplits * maxw;
+  A(&v->kpart, v->kpart_floats);
+  A(&v->rtmp, (size_t)kSumGroups * D);
   A(&v->lossp, (size_t)loss_blocks(Ta * P));
   A(&v->loss, 1);
   return e;
@@ -320,13 +330,32 @@ hipError_t run_forward(ensf_vit* v, const float* x, const float* target, float* 
 }
 
 // weight gradient dW = dY^T X from the transposed copies (rows x T_all each) and the bias
-// gradient from the row sums of dY^T
+// gradient from the row sums of dY^T.  The contraction runs over all tokens of the batch
+// while the output (out x in) may have few tiles: it is split so that about 1024
+// workgroups run, the partial products summed in split order (FP64) afterwards.
 hipError_t weight_grad(ensf_vit* v, const Lin& l, const uint16_t* dyt, const uint16_t* xt,
                        int64_t Ta, hipStream_t s) {
   VGemm g = prod(mat(dyt, Ta), mat(xt, Ta), l.out, l.in, (int)Ta);
-  g.f32 = v->g + l.w;
-  g.ld_f32 = l.in;
-  hipError_t e = launch_vgemm(g, 1, s);
+  const int tile = (l.out % 128 == 0 && l.in % 128 == 0) ? 128 : (l.out % 64 == 0 && l.in % 64 == 0) ? 64 : 32;
+  const int64_t tiles = (int64_t)(l.out / tile) * (l.in / tile);
+  int splits = (int)std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, 1024 / tiles));
+  while (splits > 1 && Ta / splits < 256) --splits;
+  hipError_t e;
+  if (splits > 1) {
+    g.kchunk = (Ta / splits + 31) / 32 * 32;
+    splits = (int)((Ta + g.kchunk - 1) / g.kchunk);
+    g.splits = splits;
+    g.part_stride = (int64_t)l.out * l.in;
+    g.f32 = v->kpart;
+    g.ld_f32 = l.in;
+    e = launch_vgemm(g, 1, s);
+    if (e == hipSuccess)
+      e = launch_sum_rows(v->kpart, splits, (int64_t)l.out * l.in, v->g + l.w, false, s);
+  } else {
+    g.f32 = v->g + l.w;
+    g.ld_f32 = l.in;
+    e = launch_vgemm(g, 1, s);
+  }
   if (e != hipSuccess) return e;
   return launch_rowsum_bf16(dyt, l.out, Ta, Ta, v->g + l.b, s);
 }
@@ -336,8 +365,8 @@ hipError_t ln_backward(ensf_vit* v, const float* xin, const float* mean, const f
   const int D = v->D;
   hipError_t e = launch_ln_bwd(v->dx32, xin, mean, rstd, v->w + g_off, Ta, D, v->dres,
                                v->dres16, v->dres16t, Ta, v->pg, v->pb, s);
-  if (e == hipSuccess) e = launch_sum_rows(v->pg, Ta / 8, D, v->g + g_off, false, s);
-  if (e == hipSuccess) e = launch_sum_rows(v->pb, Ta / 8, D, v->g + b_off, false, s);
+  if (e == hipSuccess) e = launch_sum_rows(v->pg, Ta / 8, D, v->g + g_off, false, s, v->rtmp);
+  if (e == hipSuccess) e = launch_sum_rows(v->pb, Ta / 8, D, v->g + b_off, false, s, v->rtmp);
   return e;
 }
 

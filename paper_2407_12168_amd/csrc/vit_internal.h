@@ -15,7 +15,8 @@ struct VMat {
 
 // C = alpha * A B^T (M x N, contraction over K) on BF16 MFMA with FP32 accumulation, batch
 // z = zb * nh + zh over grid.y, followed by an elementwise epilogue on v = alpha acc:
-//   v += bias[n] (if bias), v += add[(m mod add_rows) * ld_add + n] (if add; add_rows 0 = M)
+//   v += bias[n] (if bias), v += add[(m mod add_rows) * ld_add + n] (if add; add_rows 0 = M,
+//   otherwise a multiple of 4)
 //   f32  (if set) <- v                              (before the activation)
 //   act 1: v = gelu(v);  act 2: v *= gelu'(gin[m * ld_gin + n])
 //   b16  (if set) <- bf16(v),  b16t (if set) <- bf16(v) at b16t[n * ld_t + m] (transposed)
@@ -37,10 +38,14 @@ struct VGemm {
   int act;
   const float* gin;
   int64_t ld_gin;
+  // split-K (unbatched products with only the FP32 output): split s of the contraction,
+  // [s * kchunk, (s + 1) * kchunk), writes its partial product to f32 + s * part_stride
+  int64_t kchunk, part_stride;
+  int splits;
 };
 
 // Tile shape for an M x N product: 128 x 128 (four waves of 64 x 64), 64 x 64 or 32 x 32;
-// M and N must be multiples of the chosen tile, K of 32.
+// M and N must be multiples of the chosen tile, K of 32 (and kchunk, when split, of 32).
 hipError_t launch_vgemm(const VGemm& g, int batch, hipStream_t s);
 
 // rows x D FP32 -> LayerNorm (population variance, eps 1e-5) -> BF16 rows y (ld D) and,
@@ -57,8 +62,11 @@ hipError_t launch_ln_bwd(const float* dy, const float* x, const float* mean, con
                          uint16_t* res16, uint16_t* res16t, int64_t ld_t, float* pg,
                          float* pb, hipStream_t s);
 // out[c] (+)= sum over the r rows of src (FP32, r x cols, fixed order, FP64 accumulation).
+// With tmp (kSumGroups x cols doubles) and r >= 64 the rows are added in kSumGroups
+// consecutive groups first, then the group sums in order.
+constexpr int kSumGroups = 64;
 hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out, bool accumulate,
-                           hipStream_t s);
+                           hipStream_t s, double* tmp = nullptr);
 // out[i] = sum over the cols entries of row i of a BF16 matrix (ld), FP64 accumulation.
 hipError_t launch_rowsum_bf16(const uint16_t* src, int64_t rows, int64_t cols, int64_t ld,
                               float* out, hipStream_t s);

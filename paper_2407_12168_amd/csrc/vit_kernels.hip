@@ -69,17 +69,23 @@ __device__ __forceinline__ void store_tile_transposed(const uint16_t* tile, int 
 // ----------------------------------------------------------------------------------------
 // C = alpha A B^T with the fused epilogue of VGemm.
 
+// Four-wave tiles are compiled for three resident waves per SIMD (three workgroups per CU,
+// whose LDS stages also fit): the register budget that leaves is enough without spills.
 template <int WGM, int WGN, int TM, int TN>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_vgemm(VGemm g) {
+__global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1) void k_vgemm(VGemm g) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32, BK = 32;
   using S = TileSmem<kBF16, BM, BN, BK, false>;
   constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = (int)(gridDim.x / g.splits);
+  const int lt = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = lt / ntiles, tile = lt - split * ntiles;
   const int tn = tile % g.tiles_n, tm = tile / g.tiles_n;
   const int z = blockIdx.y, zb = z / g.nh, zh = z - zb * g.nh;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t kbeg = g.kchunk ? split * g.kchunk : 0;
+  const int64_t kend = g.kchunk ? min(kbeg + g.kchunk, (int64_t)g.K) : (int64_t)g.K;
 
   f32x16_t acc[TM][TN];
 #pragma unroll
@@ -96,53 +102,65 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_vgemm(VGemm g) {
   la.init(pa, pa, g.A.ld, m0);
   lb.init(pb, pb, g.B.ld, n0);
   tile_k_loop<kBF16, WGM, WGN, TM, TN, BK, PP, false>(
-      smem, 0, g.K,
+      smem, kbeg, kend,
       [&](int64_t kb) {
         la.load(kb);
         lb.load(kb);
       },
       [&](char* st) {
         uint16_t* sAh = reinterpret_cast<uint16_t*>(st);
-        uint16_t* sAl = sAh + BM * S::LDH;
-        uint16_t* sBh = sAl + BM * S::LDH;
-        la.store(sAh, sAl, S::LDH);
-        lb.store(sBh, sBh + BN * S::LDH, S::LDH);
+        la.store(sAh, sAh + S::kALo, S::LDH);
+        lb.store(sAh + S::kBHi, sAh + S::kBLo, S::LDH);
       },
       acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  float* f32 = g.f32 ? g.f32 + zb * g.sb_f32 + zh * g.sh_f32 : nullptr;
-  uint16_t* b16 = g.b16 ? g.b16 + zb * g.sb_b16 + zh * g.sh_b16 : nullptr;
-  uint16_t* b16t = g.b16t ? g.b16t + zb * g.sb_t + zh * g.sh_t : nullptr;
+  // output bases at the tile's corner: the offsets inside the tile, and the addend's row
+  // offsets (token counts times widths), fit 32 bits
+  float* f32 = g.f32 ? g.f32 + zb * g.sb_f32 + zh * g.sh_f32 + split * g.part_stride +
+                           m0 * g.ld_f32 + n0
+                     : nullptr;
+  uint16_t* b16 = g.b16 ? g.b16 + zb * g.sb_b16 + zh * g.sh_b16 + m0 * g.ld_b16 + n0 : nullptr;
+  uint16_t* b16t = g.b16t ? g.b16t + zb * g.sb_t + zh * g.sh_t + n0 * g.ld_t + m0 : nullptr;
+  const float* add = g.add ? g.add + n0 : nullptr;
+  const float* gin = g.gin ? g.gin + m0 * g.ld_gin + n0 : nullptr;
+  const int ldf = (int)g.ld_f32, ldb = (int)g.ld_b16, ldt = (int)g.ld_t;
+  const int lda = (int)g.ld_add, ldg = (int)g.ld_gin;
 #pragma unroll
   for (int b = 0; b < TN; ++b) {
-    const int64_t n = n0 + wn * TN * 32 + b * 32 + (lane & 31);
-    const float bias = g.bias ? g.bias[n] : 0.0f;
+    const int nl = wn * TN * 32 + b * 32 + (lane & 31);
+    const float bias = g.bias ? g.bias[n0 + nl] : 0.0f;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
       for (int gq = 0; gq < 4; ++gq) {
-        const int64_t mb = m0 + wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+        const int ml = wm * TM * 32 + a * 32 + gq * 8 + (lane >> 5) * 4;
+        // addend rows: add_rows is a multiple of 4, so the four rows ml..ml+3 are consecutive
+        // rows of the addend too
+        const int ar = g.add_rows ? (int)((m0 + ml) % g.add_rows) : (int)(m0 + ml);
         uint16_t h[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t m = mb + j;
+          const int m = ml + j;
           float v = g.alpha * acc[a][b][gq * 4 + j] + bias;
-          if (g.add) v += g.add[(g.add_rows ? m % g.add_rows : m) * g.ld_add + n];
-          if (f32) f32[m * g.ld_f32 + n] = v;
+          if (add) v += add[(ar + j) * lda + nl];
+          if (f32) f32[m * ldf + nl] = v;
           if (g.act == 1)
             v = gelu_f(v);
           else if (g.act == 2)
-            v *= gelu_grad_f(g.gin[m * g.ld_gin + n]);
+            v *= gelu_grad_f(gin[m * ldg + nl]);
           h[j] = to_bf16(v);
-          if (b16) b16[m * g.ld_b16 + n] = h[j];
+          if (b16) b16[m * ldb + nl] = h[j];
         }
         if (b16t) {
           const uint2 w = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
                                      (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-          *reinterpret_cast<uint2*>(b16t + n * g.ld_t + mb) = w;
+          *reinterpret_cast<uint2*>(b16t + nl * ldt + ml) = w;
         }
+        // one register group at a time: keeps the loads and addresses of the other groups
+        // from being hoisted (which costs registers, hence occupancy)
+        __builtin_amdgcn_sched_barrier(0);
       }
   }
 }
@@ -253,6 +271,27 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float* src, int64_t r, i
   if (c >= cols) return;
   double s = 0.0;
   for (int64_t i = 0; i < r; ++i) s += src[i * cols + c];
+  out[c] = accumulate ? (float)(out[c] + s) : (float)s;
+}
+
+// First level of a two-level column sum: group g of G adds rows [g r / G, (g + 1) r / G)
+// in order into tmp[g][c] (FP64).
+__global__ __launch_bounds__(256) void k_sum_rows_groups(const float* src, int64_t r,
+                                                         int64_t cols, double* tmp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y, G = gridDim.y;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int64_t i = g * r / G; i < (g + 1) * r / G; ++i) s += src[i * cols + c];
+  tmp[g * cols + c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_groups(const double* tmp, int G, int64_t cols,
+                                                    float* out, int accumulate) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += tmp[g * cols + c];
   out[c] = accumulate ? (float)(out[c] + s) : (float)s;
 }
 
@@ -463,9 +502,13 @@ inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / p
 hipError_t launch_vgemm(const VGemm& g0, int batch, hipStream_t s) {
   VGemm g = g0;
   if (g.K % 32 != 0 || g.K <= 0) return hipErrorInvalidValue;
+  if (g.splits < 1) g.splits = 1;
+  if (g.splits > 1 && (g.kchunk % 32 != 0 || g.kchunk * g.splits < g.K || batch != 1))
+    return hipErrorInvalidValue;
   auto go = [&](auto kern, int bm, int bn, int threads) {
     g.tiles_n = g.N / bn;
-    hipLaunchKernelGGL(kern, dim3((unsigned)((g.M / bm) * (g.N / bn)), (unsigned)batch),
+    hipLaunchKernelGGL(kern, dim3((unsigned)((g.M / bm) * (g.N / bn) * g.splits),
+                                  (unsigned)batch),
                        dim3(threads), 0, s, g);
     return hipGetLastError();
   };
@@ -511,7 +554,15 @@ hipError_t launch_ln_bwd(const float* dy, const float* x, const float* mean, con
 }
 
 hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out, bool accumulate,
-                           hipStream_t s) {
+                           hipStream_t s, double* tmp) {
+  if (tmp && r >= 64) {
+    const int G = kSumGroups;
+    hipLaunchKernelGGL(k_sum_rows_groups, dim3(blocks(cols, 256), G), dim3(256), 0, s, src, r,
+                       cols, tmp);
+    hipLaunchKernelGGL(k_sum_groups, dim3(blocks(cols, 256)), dim3(256), 0, s, tmp, G, cols, out,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_sum_rows, dim3(blocks(cols, 256)), dim3(256), 0, s, src, r, cols, out,
                      accumulate ? 1 : 0);
   return hipGetLastError();
