@@ -11,8 +11,8 @@
 //
 // The input-gradient convolution is the same kernel run on the output gradient with the
 // taps flipped and the weight matrix transposed.  The weight gradient contracts over
-// pixels, which are strided in NHWC, so it stages FP32 tiles k-major in LDS and uses
-// v_mfma_f32_32x32x2_f32; per-chunk partials are reduced in a fixed order.
+// pixels, which are strided in NHWC, so it stages BF16 tiles channel-major in LDS and uses
+// v_mfma_f32_32x32x16_bf16; per-chunk partials are reduced in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -176,13 +176,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
 
 // ---------------------------------------------------------------------------------------
 // weight gradient: part[chunk][tap][co][ci] = sum_{p in chunk} du[p][co] * in[p + tap][ci]
+// on v_mfma_f32_32x32x16_bf16 (the operands are the BF16 activations and output gradients;
+// FP32 accumulation).  The contraction runs over pixels, which are strided in NHWC, so each
+// k-step of KS pixels is staged channel-major in LDS ([channel][pixel], rows padded to
+// KS + 8): a thread loads eight channels of two consecutive pixels (two 16-byte loads) and
+// writes the eight (pixel, pixel + 1) pairs as 4-byte words; a lane then reads the 8
+// consecutive pixels of its channel as one 16-byte fragment.
 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
-  constexpr int KS = 32;                  // pixels per k-step (one row segment)
-  constexpr int LDA = COUT + 4, LDB = CIN + 4;
-  __shared__ float sA[KS * LDA];
-  __shared__ float sB[KS * LDB];
+  constexpr int KS = 64;                  // pixels per k-step
+  constexpr int LDK = KS + 8;             // LDS row (one channel), bf16
+  __shared__ __attribute__((aligned(16))) uint16_t sA[COUT * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[CIN * LDK];
   constexpr int WM = COUT / 32, WN = CIN / 32;
   const int H = args.H, W = args.W;
   const int chunk = blockIdx.x, tap = blockIdx.y;
@@ -194,48 +200,45 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
   const bool active = wave < WM * WN;
   const int wm = wave / WN, wn = wave % WN;
 
+  // staging unit of this thread: pixel pair pp, channel octet c8
+  auto stage = [&](uint16_t* dst, int C, auto src_of, int64_t pb) {
+    for (int v = tid; v < (KS / 2) * (C / 8); v += 256) {
+      const int pp = v % (KS / 2), c8 = v / (KS / 2);
+      u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
+      const int64_t p = pb + 2 * pp;
+      if (p < p1) w0 = *reinterpret_cast<const u32x4*>(src_of(p) + c8 * 8);
+      if (p + 1 < p1) w1 = *reinterpret_cast<const u32x4*>(src_of(p + 1) + c8 * 8);
+      uint32_t* d = reinterpret_cast<uint32_t*>(dst + (c8 * 8) * LDK + 2 * pp);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[(2 * q) * (LDK / 2)] = (w0[q] & 0xFFFFu) | (w1[q] << 16);
+        d[(2 * q + 1) * (LDK / 2)] = (w0[q] >> 16) | (w1[q] & 0xFFFF0000u);
+      }
+    }
+  };
+  auto du_row = [&](int64_t p) { return args.du + p * COUT; };
+  auto in_row = [&](int64_t p) {
+    const int64_t bimg = p / ((int64_t)H * W);
+    const int yy = (int)((p / W) % H), xx = (int)(p % W);
+    return args.in + ((bimg * H + wrap(yy + dy, H)) * W + wrap(xx + dx, W)) * CIN;
+  };
+
   f32x16_t acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
   for (int64_t pb = p0; pb < p1; pb += KS) {
     __syncthreads();
-    for (int v = tid; v < KS * COUT / 8; v += 256) {
-      const int k = v / (COUT / 8), c8 = v % (COUT / 8);
-      const int64_t p = pb + k;
-      u32x4 w = {0, 0, 0, 0};
-      if (p < p1) w = *reinterpret_cast<const u32x4*>(args.du + p * COUT + c8 * 8);
-      float* d = sA + k * LDA + c8 * 8;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[2 * q] = from_bf16((uint16_t)(w[q] & 0xFFFF));
-        d[2 * q + 1] = from_bf16((uint16_t)(w[q] >> 16));
-      }
-    }
-    for (int v = tid; v < KS * CIN / 8; v += 256) {
-      const int k = v / (CIN / 8), c8 = v % (CIN / 8);
-      const int64_t p = pb + k;
-      u32x4 w = {0, 0, 0, 0};
-      if (p < p1) {
-        const int64_t bimg = p / ((int64_t)H * W);
-        const int yy = (int)((p / W) % H), xx = (int)(p % W);
-        const int64_t q = (bimg * H + wrap(yy + dy, H)) * W + wrap(xx + dx, W);
-        w = *reinterpret_cast<const u32x4*>(args.in + q * CIN + c8 * 8);
-      }
-      float* d = sB + k * LDB + c8 * 8;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[2 * q] = from_bf16((uint16_t)(w[q] & 0xFFFF));
-        d[2 * q + 1] = from_bf16((uint16_t)(w[q] >> 16));
-      }
-    }
+    stage(sA, COUT, du_row, pb);
+    stage(sB, CIN, in_row, pb);
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int kk = 0; kk < KS; kk += 2) {
-        const float a = sA[(kk + (lane >> 5)) * LDA + wm * 32 + (lane & 31)];
-        const float bb = sB[(kk + (lane >> 5)) * LDB + wn * 32 + (lane & 31)];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+      for (int kk = 0; kk < KS; kk += 16) {
+        const int o = kk + (lane >> 5) * 8;
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(sA + (wm * 32 + (lane & 31)) * LDK + o);
+        const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(sB + (wn * 32 + (lane & 31)) * LDK + o);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     }
   }

@@ -3,8 +3,9 @@ model, learned forecast by the trained conv surrogate, split-BF16 EnSF analysis.
 
 Checks: the cycle stays finite and bounded; at the observed components the analysis
 error is below the forecast error every cycle; the trained network is a useful forecast
-model (validation error well below persistence, and its cycled analysis beats carrying the
-analysis over without a forecast model).  In this twin setting the physics forecast is the
+model (validation error well below persistence, its cycled analysis beats carrying the
+analysis over without a forecast model, and its mean analysis RMSE stays within
+CONV_VS_SPECTRAL of the spectral forecast's).  In this twin setting the physics forecast is the
 truth's own model, so the network's expected gain over it is speed (reported).
 """
 import numpy as np
@@ -23,6 +24,9 @@ def dev():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
 
+
+# bar on the mean analysis RMSE of the learned-forecast cycle relative to the spectral one
+CONV_VS_SPECTRAL = 1.5
 
 CFG = cycle.CycleConfig(grid=64, members=64, cycles=6, pseudo_steps=400, sqg_dt=0.025,
                         steps_per_cycle=10, spinup_steps=800)
@@ -52,3 +56,7 @@ def test_trained_surrogate_beats_no_forecast_and_tracks_physics(dev):
           f"forecast ms conv {1e3 * np.mean(conv.forecast_s):.2f}, "
           f"sqg {1e3 * np.mean(phys.forecast_s):.2f}")
     assert f(conv) < f(pers)
+    # the spectral forecast is the truth's own model in this twin experiment, so the learned
+    # forecast cannot beat it on accuracy; it must keep the analysis within a factor of it
+    # (the full-size cycle measures 0.88x: the network forecast is also smoother)
+    assert m(conv) < CONV_VS_SPECTRAL * m(phys)
