@@ -93,7 +93,12 @@ typedef struct {
   double  eps_alpha;      /* schedule floor eps in alpha_t = 1 - t (1 - eps); default 0.05 */
   double  spread_relax;   /* r in [0, 1]: relax the analysis spread toward the prior
                              spread per component (Sec. IV-A); 0 = off */
-  int32_t use_graph;      /* 1: run the pseudo-time loop as a captured hipGraph */
+  int32_t use_graph;      /* pseudo-time loop: 0 eager launches; 1 (default) and 3 one
+                             captured hipGraph; 2 one cooperative launch that runs every
+                             pseudo-step with grid-wide barriers between its phases, when the
+                             tile table gives the Gram 64 x 64 / W.X 128 x 32 tiles with k-step
+                             32 and one LDS stage (else the graph).  All give bit-identical
+                             results; the graph is the faster on MI355X. */
   int32_t device;         /* HIP device ordinal the context lives on */
   const char* tune_cache; /* JSON tile-table path for the autotuner; NULL = $ENSF_TUNE_CACHE */
   int32_t lik_step;       /* ensf_lik_step; default EXPLICIT */

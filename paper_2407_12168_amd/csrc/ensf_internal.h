@@ -133,6 +133,21 @@ hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ld
 hipError_t launch_wx(int prec, int cfg, int bk, int st, bool score_mode, bool sparse,
                      const GroupedLaunch& g, int step, unsigned long long* nonfinite,
                      hipStream_t s);
+// The pseudo-time loop of a grouped launch in one cooperative launch (ensf_kernels.hip).
+struct PersistArgs {
+  GroupedLaunch gram, rows, wx;
+  int kmax, max_ldn;
+  unsigned* bar;                    // barrier arrivals, zero before the launch
+  unsigned* err;                    // set when a barrier wait gave up
+  unsigned long long* nonfinite;
+  int spin_limit;
+};
+// Tile variants the persistent kernel is built for: Gram kGram64, W.X kWx32, k-step 32, one
+// LDS stage, FP32 or split BF16.
+bool persistent_tiles(int prec, int gram, int gram_bk, int gram_st, int wx, int wx_bk, int wx_st);
+// Launches it with at most max_blocks workgroups (all co-resident; cooperative launch).
+hipError_t launch_persistent(int prec, const PersistArgs& a, int max_blocks, hipStream_t s);
+
 // Observation densification (ensf_densify.hip): deterministic A and B, any duplicates.
 hipError_t launch_densify(const ProbDev& p, unsigned long long* bad_obs, hipStream_t s);
 hipError_t launch_prep_rows(int prec, const ProbDev& p, hipStream_t s);

@@ -20,6 +20,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "ensf_internal.h"
@@ -141,13 +142,19 @@ __device__ __forceinline__ float update_step(float z, float xh, float a_e, float
 // Gram: part[s][i][j] = sum_{k in chunk s} Z[i][k] X[j][k]
 
 template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
+struct GramShape {
+  static constexpr int BM = WGM * TM * 32, BN = WGN * TN * 32;
+  using S = TileSmem<PREC, BM, BN, BK, false>;
+  static constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
+  static constexpr int kSmem = PP ? 2 * S::kBytes : S::kBytes;
+};
+
+// One logical Gram tile (particle block x member block x split-K chunk) of a grouped launch.
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
+__device__ __forceinline__ void gram_tile(const GroupedLaunch& g, int step, int tile, char* smem) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
   using S = TileSmem<PREC, BM, BN, BK, false>;
-  constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
-  __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
-
-  const int tile = xcd_remap(blockIdx.x, g.total);
+  constexpr bool PP = GramShape<PREC, WGM, WGN, TM, TN, BK, ST>::PP;
   const int f = find_problem(g.pre, g.np, tile);
   const ProbDev& P = g.desc[f];
   if (step >= P.K) return;
@@ -219,6 +226,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int st
         gstore(out + (a * 32 + (r >> 2) * 8 + (r & 3)) * ldn + b * 32, acc[a][b][r]);
 }
 
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gram(GroupedLaunch g, int step) {
+  __shared__ __attribute__((aligned(16)))
+      char smem[GramShape<PREC, WGM, WGN, TM, TN, BK, ST>::kSmem];
+  gram_tile<PREC, WGM, WGN, TM, TN, BK, ST>(g, step, xcd_remap(blockIdx.x, g.total), smem);
+}
+
 // ----------------------------------------------------------------------------------------
 // Row softmax of the logits (eq. 16), one workgroup of 256 per particle row.  The split-K
 // partials are summed in FP64 in a fixed order (deterministic): thread groups take
@@ -247,12 +261,10 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* red) {
   return v;
 }
 
+// One particle row of the grouped launch, 256 threads; sL holds ldn doubles, sG 1024, red 8.
 template <int PREC>
-__global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
-  extern __shared__ double sL[];            // ldn logits of the row
-  __shared__ double sG[256 * 4];            // per-group partial sums (4 components each)
-  __shared__ double red[8];
-  const int row = blockIdx.x;
+__device__ __forceinline__ void softmax_row(const GroupedLaunch& g, int step, int row, double* sL,
+                                            double* sG, double* red) {
   const int f = find_problem(g.pre, g.np, row);
   const ProbDev& P = g.desc[f];
   if (step >= P.K) return;
@@ -356,6 +368,14 @@ __global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
     }
     if (tid == 0) P.sp_cnt[i] = cnt;
   }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_softmax(GroupedLaunch g, int step) {
+  extern __shared__ double sL[];            // ldn logits of the row
+  __shared__ double sG[256 * 4];            // per-group partial sums (4 components each)
+  __shared__ double red[8];
+  softmax_row<PREC>(g, step, blockIdx.x, sL, sG, red);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -536,18 +556,24 @@ __device__ __forceinline__ void wx_epilogue(const WxEpi& E, const f32x16_t (&acc
     }
 }
 
-template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE, bool SP = false>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
-                                                       unsigned long long* nonfinite) {
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST>
+struct WxShape {
+  static constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
+  using S = TileSmem<PREC, BE, BP, BK, true>;
+  static constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
+  // the epilogue stages one 32 x 32 FP32 block per wave through the operand buffer
+  static constexpr int kStage = NT / 64 * 4096;
+  static constexpr int kOps = PP ? 2 * S::kBytes : S::kBytes;
+  static constexpr int kSmem = kOps > kStage ? kOps : kStage;
+};
+
+// One logical W.X tile (component block x particle block) of a grouped launch.
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE, bool SP>
+__device__ __forceinline__ void wx_tile(const GroupedLaunch& g, int step, int tile,
+                                        unsigned long long* nonfinite, char* smem) {
   constexpr int NT = 64 * WGM * WGN, BE = WGM * TM * 32, BP = WGN * TN * 32;
   using S = TileSmem<PREC, BE, BP, BK, true>;
-  constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
-  // the epilogue stages one 32 x 32 FP32 block per wave through the operand buffer
-  constexpr int kStage = NT / 64 * 4096;
-  constexpr int kSmem = PP ? 2 * S::kBytes : S::kBytes;
-  __shared__ __attribute__((aligned(16))) char smem[kSmem > kStage ? kSmem : kStage];
-
-  const int tile = xcd_remap(blockIdx.x, g.total);
+  constexpr bool PP = WxShape<PREC, WGM, WGN, TM, TN, BK, ST>::PP;
   const int f = find_problem(g.pre, g.np, tile);
   const ProbDev& P = g.desc[f];
   if (!SCORE && step >= P.K) return;
@@ -638,6 +664,78 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step
     if (E.implicit && !SCORE) epilogue(LinT{}, Yes{}); else epilogue(LinT{}, No{});
   }
   if (!SCORE && bad) atomicAdd(nonfinite, (unsigned long long)bad);
+}
+
+template <int PREC, int WGM, int WGN, int TM, int TN, int BK, int ST, bool SCORE, bool SP = false>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_wx(GroupedLaunch g, int step,
+                                                       unsigned long long* nonfinite) {
+  __shared__ __attribute__((aligned(16)))
+      char smem[WxShape<PREC, WGM, WGN, TM, TN, BK, ST>::kSmem];
+  wx_tile<PREC, WGM, WGN, TM, TN, BK, ST, SCORE, SP>(g, step, xcd_remap(blockIdx.x, g.total),
+                                                     nonfinite, smem);
+}
+
+// ----------------------------------------------------------------------------------------
+// The whole pseudo-time loop in one cooperative launch, for problems too small to fill the
+// device, where three graph nodes per pseudo-step cost more in launch latency than their
+// work.  Every pseudo-step runs the Gram tiles, the softmax rows and the W.X tiles of the
+// grouped launches, each strided over the grid with the same per-tile code as the separate
+// kernels (hence bit-identical results), separated by grid-wide barriers.  Tile shapes:
+// Gram 64 x 64 on four waves, W.X 128 components x 32 particles on four waves, k-step 32,
+// one LDS stage.
+
+// Grid-wide barrier number n (targets n * gridDim.x arrivals on a counter that starts at 0).
+// The wait is bounded: after spin_limit polls the barrier gives up and raises *err, which the
+// host reports, so every workgroup always finishes.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, unsigned* err,
+                                             int spin_limit) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int it = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++it > spin_limit) {
+        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+template <int PREC>
+using PersistGS = GramShape<PREC, 2, 2, 1, 1, 32, 1>;
+template <int PREC>
+using PersistWS = WxShape<PREC, 4, 1, 1, 1, 32, 1>;
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_persistent(PersistArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char psmem[];
+  double* sL = reinterpret_cast<double*>(psmem);     // softmax: ldn logits, 1024 group sums,
+  double* sG = sL + a.max_ldn;                       // 8 reduction slots
+  double* red = sG + 1024;
+  const unsigned G = gridDim.x;
+  unsigned n = 0;
+  for (int k = 0; k < a.kmax; ++k) {
+    for (int t = blockIdx.x; t < a.gram.total; t += G) {
+      gram_tile<PREC, 2, 2, 1, 1, 32, 1>(a.gram, k, t, psmem);
+      __syncthreads();
+    }
+    grid_barrier(a.bar, (++n) * G, a.err, a.spin_limit);
+    for (int r = blockIdx.x; r < a.rows.total; r += G) {
+      softmax_row<PREC>(a.rows, k, r, sL, sG, red);
+      __syncthreads();
+    }
+    grid_barrier(a.bar, (++n) * G, a.err, a.spin_limit);
+    for (int t = blockIdx.x; t < a.wx.total; t += G) {
+      wx_tile<PREC, 4, 1, 1, 1, 32, 1, false, false>(a.wx, k, t, a.nonfinite, psmem);
+      __syncthreads();
+    }
+    grid_barrier(a.bar, (++n) * G, a.err, a.spin_limit);
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -872,6 +970,41 @@ hipError_t launch_softmax(int prec, const GroupedLaunch& g, int step, int max_ld
     hipLaunchKernelGGL(k_softmax<kBF16>, dim3(g.total), dim3(256), shm, s, g, step);
   }
   return hipGetLastError();
+}
+
+bool persistent_tiles(int prec, int gram, int gram_bk, int gram_st, int wx, int wx_bk,
+                      int wx_st) {
+  return (prec == kFP32 || prec == kBF16X3) && gram == kGram64 && gram_bk == 32 &&
+         gram_st == 1 && wx == kWx32 && wx_bk == 32 && wx_st == 1;
+}
+
+hipError_t launch_persistent(int prec, const PersistArgs& a, int max_blocks, hipStream_t s) {
+  auto go = [&](const void* fn, size_t ops) -> hipError_t {
+    const size_t shm = std::max(ops, (size_t)(a.max_ldn + 1024 + 8) * sizeof(double));
+    hipError_t e = hipSuccess;
+    if (shm > 64 * 1024)
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, shm)) != hipSuccess)
+      return e;
+    const int work = std::max({a.gram.total, a.rows.total, a.wx.total});
+    const int blocks = std::min({work, per_cu * prop.multiProcessorCount, max_blocks});
+    if (blocks < 1) return hipErrorInvalidConfiguration;
+    PersistArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), params, (unsigned)shm, s);
+  };
+  if (prec == kFP32)
+    return go(reinterpret_cast<const void*>(k_persistent<kFP32>),
+              std::max(PersistGS<kFP32>::kSmem, PersistWS<kFP32>::kSmem));
+  if (prec == kBF16X3)
+    return go(reinterpret_cast<const void*>(k_persistent<kBF16X3>),
+              std::max(PersistGS<kBF16X3>::kSmem, PersistWS<kBF16X3>::kSmem));
+  return hipErrorInvalidValue;
 }
 
 hipError_t set_softmax_smem_limit(size_t bytes) {

@@ -253,23 +253,33 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
   }
 }
 
-// bias gradient partials: part[chunk][co] = sum_{p in chunk} du[p][co]
+// bias gradient partials: part[chunk][co] = sum_{p in chunk} du[p][co].  Thread t reads the
+// channel octet t % (cout / 8) of pixels t / (cout / 8), + lanes, ... as 16-byte vectors
+// (a block reads whole consecutive pixel rows), then the per-lane sums are added in lane
+// order through LDS.
 __global__ __launch_bounds__(256) void k_bias_grad_part(const uint16_t* __restrict__ du,
                                                        int64_t npix, int cout, int chunk_pixels,
                                                        float* __restrict__ part) {
-  __shared__ float s[256];
-  const int groups = 256 / cout;
-  const int co = threadIdx.x % cout, grp = threadIdx.x / cout;
+  __shared__ float s[256 * 8];
+  const int octets = cout / 8, lanes = 256 / octets;
+  const int o = threadIdx.x % octets, pl = threadIdx.x / octets;
   const int64_t p0 = (int64_t)blockIdx.x * chunk_pixels;
   const int64_t p1 = min(p0 + (int64_t)chunk_pixels, npix);
-  float acc = 0.0f;
-  if (grp < groups)
-    for (int64_t p = p0 + grp; p < p1; p += groups) acc += from_bf16(du[p * cout + co]);
-  s[threadIdx.x] = acc;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t p = p0 + pl; p < p1; p += lanes) {
+    const u32x4 w = *reinterpret_cast<const u32x4*>(du + p * cout + o * 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[2 * q] += from_bf16((uint16_t)(w[q] & 0xFFFFu));
+      acc[2 * q + 1] += from_bf16((uint16_t)(w[q] >> 16));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s[pl * cout + o * 8 + c] = acc[c];
   __syncthreads();
   if (threadIdx.x < cout) {
     float t = 0.0f;
-    for (int gg = 0; gg < groups; ++gg) t += s[gg * cout + threadIdx.x];
+    for (int l = 0; l < lanes; ++l) t += s[l * cout + threadIdx.x];
     part[(int64_t)blockIdx.x * cout + threadIdx.x] = t;
   }
 }

@@ -164,7 +164,9 @@ def make_options(precision="fp32", obs_op="arctan", eps_alpha=0.05, spread_relax
     o.obs_op = OBS_OPS[obs_op] if isinstance(obs_op, str) else int(obs_op)
     o.eps_alpha = eps_alpha
     o.spread_relax = spread_relax
-    o.use_graph = 1 if use_graph else 0
+    # True/False, or the ensf_options value: 0 eager, 1 or 3 graph, 2 one cooperative launch
+    # (persistent pseudo-time loop) when the tiles allow it
+    o.use_graph = int(use_graph) if not isinstance(use_graph, bool) else (1 if use_graph else 0)
     o.device = device
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.lik_step = LIK_STEPS[lik_step] if isinstance(lik_step, str) else int(lik_step)
