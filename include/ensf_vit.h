@@ -17,8 +17,9 @@
  * master weights.
  *
  * Numerics: every matrix product (forward, input and weight gradients, attention) has BF16
- * operands and FP32 accumulation on MFMA; the residual stream, pre-activations, LayerNorm
- * statistics, the loss and the optimizer state are FP32.
+ * operands and FP32 accumulation on MFMA; the residual stream, LayerNorm statistics, the
+ * loss and the optimizer state are FP32; the GELU derivative at the MLP pre-activation is
+ * kept for the backward pass in BF16.
  *
  * Parameters cross the ABI flat, float32, host memory, in this order: W_pe (D x P), b_pe (D),
  * pos (T x D); per layer ln1 gamma, beta (D), W_qkv (3D x D), b_qkv (3D), W_o (D x D),

@@ -36,7 +36,7 @@ struct Layer {
   uint16_t* P16; uint16_t* Pt16;   // attention weights (B*heads x T x T) and per-batch transpose
   uint16_t* o16; uint16_t* o16t;   // attention output (concatenated heads)
   uint16_t* m16; uint16_t* m16t;   // LN2 output
-  float* u32;                      // fc1 pre-activation
+  uint16_t* gp16;                  // GELU'(fc1 pre-activation), BF16
   uint16_t* g16; uint16_t* g16t;   // GELU output
 };
 
@@ -158,7 +158,7 @@ hipError_t allocate(ensf_vit* v) {
     A(&ly.P16, Z * TT); A(&ly.Pt16, Z * TT);
     A(&ly.o16, Ta * D); A(&ly.o16t, Ta * D);
     A(&ly.m16, Ta * D); A(&ly.m16t, Ta * D);
-    A(&ly.u32, Ta * F);
+    A(&ly.gp16, Ta * F);
     A(&ly.g16, Ta * F); A(&ly.g16t, Ta * F);
   }
   A(&v->meanf, Ta); A(&v->rstdf, Ta);
@@ -290,9 +290,9 @@ hipError_t run_forward(ensf_vit* v, const float* x, const float* target, float* 
       const Lin& l = v->lins[ly.fc1];
       VGemm g = prod(mat(ly.m16, D), mat(l.w16, D), (int)Ta, F, D);
       g.bias = w + l.b;
-      g.f32 = ly.u32;
-      g.ld_f32 = F;
       g.act = 1;
+      g.gd = ly.gp16;
+      g.ld_gin = F;
       g.b16 = ly.g16;
       g.ld_b16 = F;
       g.b16t = ly.g16t;
@@ -396,7 +396,7 @@ hipError_t run_backward(ensf_vit* v, int nb, hipStream_t s) {
     {
       VGemm g = prod(mat(v->dres16, D), mat(l2.w16t, D), (int)Ta, F, D);
       g.act = 2;
-      g.gin = ly.u32;
+      g.gin = ly.gp16;
       g.ld_gin = F;
       g.b16 = v->du16;
       g.ld_b16 = F;

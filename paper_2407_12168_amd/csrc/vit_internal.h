@@ -18,7 +18,8 @@ struct VMat {
 //   v += bias[n] (if bias), v += add[(m mod add_rows) * ld_add + n] (if add; add_rows 0 = M,
 //   otherwise a multiple of 4)
 //   f32  (if set) <- v                              (before the activation)
-//   act 1: v = gelu(v);  act 2: v *= gelu'(gin[m * ld_gin + n])
+//   act 1: gd[m * ld_gin + n] <- bf16(gelu'(v)) (if gd), then v = gelu(v);
+//   act 2: v *= gin[m * ld_gin + n] (a BF16 derivative written by an act 1 product)
 //   b16  (if set) <- bf16(v),  b16t (if set) <- bf16(v) at b16t[n * ld_t + m] (transposed)
 // add and gin are used only by unbatched products.
 struct VGemm {
@@ -36,7 +37,8 @@ struct VGemm {
   uint16_t* b16t;
   int64_t ld_t, sb_t, sh_t;
   int act;
-  const float* gin;
+  const uint16_t* gin;
+  uint16_t* gd;
   int64_t ld_gin;
   // split-K (unbatched products with only the FP32 output): split s of the contraction,
   // [s * kchunk, (s + 1) * kchunk), writes its partial product to f32 + s * part_stride

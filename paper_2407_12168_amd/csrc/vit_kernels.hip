@@ -124,7 +124,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1) void k_vgem
   uint16_t* b16 = g.b16 ? g.b16 + zb * g.sb_b16 + zh * g.sh_b16 + m0 * g.ld_b16 + n0 : nullptr;
   uint16_t* b16t = g.b16t ? g.b16t + zb * g.sb_t + zh * g.sh_t + n0 * g.ld_t + m0 : nullptr;
   const float* add = g.add ? g.add + n0 : nullptr;
-  const float* gin = g.gin ? g.gin + m0 * g.ld_gin + n0 : nullptr;
+  const uint16_t* gin = g.gin ? g.gin + m0 * g.ld_gin + n0 : nullptr;
+  uint16_t* gd = g.gd ? g.gd + m0 * g.ld_gin + n0 : nullptr;
   const int ldf = (int)g.ld_f32, ldb = (int)g.ld_b16, ldt = (int)g.ld_t;
   const int lda = (int)g.ld_add, ldg = (int)g.ld_gin;
 #pragma unroll
@@ -146,10 +147,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1) void k_vgem
           float v = g.alpha * acc[a][b][gq * 4 + j] + bias;
           if (add) v += add[(ar + j) * lda + nl];
           if (f32) f32[m * ldf + nl] = v;
-          if (g.act == 1)
+          if (g.act == 1) {
+            if (gd) gd[m * ldg + nl] = to_bf16(gelu_grad_f(v));
             v = gelu_f(v);
-          else if (g.act == 2)
-            v *= gelu_grad_f(gin[m * ldg + nl]);
+          } else if (g.act == 2) {
+            v *= from_bf16(gin[m * ldg + nl]);
+          }
           h[j] = to_bf16(v);
           if (b16) b16[m * ldb + nl] = h[j];
         }
@@ -168,6 +171,41 @@ __global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1) void k_vgem
 // ----------------------------------------------------------------------------------------
 // LayerNorm
 
+// Rows are held in registers: lane l owns the V-wide groups (64 j + l) of its row, j < J (V = 4
+// loads and stores 16 / 8 bytes at once when D is a multiple of 256, J = D / 256; otherwise
+// V = 1 with guards up to D = 2048).
+
+template <int V>
+__device__ __forceinline__ void load_v(const float* p, float (&v)[V]) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) v[c] = p[c];
+  }
+}
+template <int V>
+__device__ __forceinline__ void store_v(float* p, const float (&v)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) p[c] = v[c];
+  }
+}
+template <int V>
+__device__ __forceinline__ void store_bf16_v(uint16_t* p, const uint16_t (&h)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                             (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) p[c] = h[c];
+  }
+}
+
+template <int V, int J>
 __global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const float* gam,
                                                 const float* bet, uint16_t* y, uint16_t* yt,
                                                 int64_t ld_t, float* mean, float* rstd) {
@@ -177,19 +215,40 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const flo
   for (int rr = wave; rr < kRows; rr += 4) {
     const int64_t r = r0 + rr;
     const float* xr = x + r * D;
+    float v[J][V];
     float s = 0.0f;
-    for (int d = lane; d < D; d += 64) s += xr[d];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) {
+        load_v<V>(xr + d0, v[j]);
+#pragma unroll
+        for (int c = 0; c < V; ++c) s += v[j][c];
+      }
+    }
     const float mu = wave_sum(s) / (float)D;
     float q = 0.0f;
-    for (int d = lane; d < D; d += 64) {
-      const float c = xr[d] - mu;
-      q += c * c;
-    }
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if ((j * 64 + lane) * V < D)
+#pragma unroll
+        for (int c = 0; c < V; ++c) q += (v[j][c] - mu) * (v[j][c] - mu);
     const float rs = 1.0f / sqrtf(wave_sum(q) / (float)D + 1e-5f);
-    for (int d = lane; d < D; d += 64) {
-      const uint16_t b = to_bf16((xr[d] - mu) * rs * gam[d] + bet[d]);
-      y[r * D + d] = b;
-      if (yt) tile[rr * (D + 2) + d] = b;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) {
+        float g[V], b[V];
+        uint16_t h[V];
+        load_v<V>(gam + d0, g);
+        load_v<V>(bet + d0, b);
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          h[c] = to_bf16((v[j][c] - mu) * rs * g[c] + b[c]);
+          if (yt) tile[rr * (D + 2) + d0 + c] = h[c];
+        }
+        store_bf16_v<V>(y + r * D + d0, h);
+      }
     }
     if (lane == 0) {
       mean[r] = mu;
@@ -202,59 +261,72 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const flo
 }
 
 // dres += LayerNorm backward of dy; BF16 copies of the updated dres; per-wave partial sums
-// of dy * xhat and dy over its 8 rows.  D <= 2048, D % 64 == 0.
+// of dy * xhat and dy over its 8 rows.
+template <int V, int J>
 __global__ __launch_bounds__(256) void k_ln_bwd(const float* dy, const float* x,
                                                 const float* mean, const float* rstd,
                                                 const float* gam, int D, float* dres,
                                                 uint16_t* res16, uint16_t* res16t,
                                                 int64_t ld_t, float* pg, float* pb) {
   extern __shared__ uint16_t tile[];   // kRows x (D + 2)
-  constexpr int kMaxJ = 2048 / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * kRows;
-  float sg[kMaxJ], sb[kMaxJ];
+  float sg[J][V], sb[J][V];
 #pragma unroll
-  for (int j = 0; j < kMaxJ; ++j) sg[j] = sb[j] = 0.0f;
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int c = 0; c < V; ++c) sg[j][c] = sb[j][c] = 0.0f;
   for (int rr = wave * 8; rr < wave * 8 + 8; ++rr) {
     const int64_t r = r0 + rr;
     const float mu = mean[r], rs = rstd[r];
-    float dv[kMaxJ], xh[kMaxJ];
+    float dv[J][V], xh[J][V];
     float s1 = 0.0f, s2 = 0.0f;
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j) {
-      const int d = j * 64 + lane;
-      if (d < D) {
-        const float g = dy[r * D + d];
-        xh[j] = (x[r * D + d] - mu) * rs;
-        dv[j] = g * gam[d];
-        s1 += dv[j];
-        s2 += dv[j] * xh[j];
-        sg[j] += g * xh[j];
-        sb[j] += g;
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) {
+        float g[V], xv[V], gm[V];
+        load_v<V>(dy + r * D + d0, g);
+        load_v<V>(x + r * D + d0, xv);
+        load_v<V>(gam + d0, gm);
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          xh[j][c] = (xv[c] - mu) * rs;
+          dv[j][c] = g[c] * gm[c];
+          s1 += dv[j][c];
+          s2 += dv[j][c] * xh[j][c];
+          sg[j][c] += g[c] * xh[j][c];
+          sb[j][c] += g[c];
+        }
       }
     }
     s1 = wave_sum(s1) / (float)D;
     s2 = wave_sum(s2) / (float)D;
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j) {
-      const int d = j * 64 + lane;
-      if (d < D) {
-        float* o = dres + r * D + d;
-        const float v = *o + rs * (dv[j] - s1 - xh[j] * s2);
-        *o = v;
-        const uint16_t b = to_bf16(v);
-        if (res16) res16[r * D + d] = b;
-        if (res16t) tile[rr * (D + 2) + d] = b;
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) {
+        float o[V];
+        uint16_t h[V];
+        load_v<V>(dres + r * D + d0, o);
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          o[c] += rs * (dv[j][c] - s1 - xh[j][c] * s2);
+          h[c] = to_bf16(o[c]);
+          if (res16t) tile[rr * (D + 2) + d0 + c] = h[c];
+        }
+        store_v<V>(dres + r * D + d0, o);
+        if (res16) store_bf16_v<V>(res16 + r * D + d0, h);
       }
     }
   }
   const int64_t prow = (r0 >> 3) + wave;
 #pragma unroll
-  for (int j = 0; j < kMaxJ; ++j) {
-    const int d = j * 64 + lane;
-    if (d < D) {
-      pg[prow * D + d] = sg[j];
-      pb[prow * D + d] = sb[j];
+  for (int j = 0; j < J; ++j) {
+    const int d0 = (j * 64 + lane) * V;
+    if (d0 < D) {
+      store_v<V>(pg + prow * D + d0, sg[j]);
+      store_v<V>(pb + prow * D + d0, sb[j]);
     }
   }
   if (!res16t) return;
@@ -301,7 +373,19 @@ __global__ __launch_bounds__(256) void k_rowsum_bf16(const uint16_t* src, int64_
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
   double s = 0.0;
-  for (int64_t c = lane; c < cols; c += 64) s += from_bf16(src[row * ld + c]);
+  const uint16_t* p = src + row * ld;
+  if ((cols & 7) == 0 && (ld & 7) == 0) {   // 8 values (16 bytes) per lane and load
+    for (int64_t c = lane * 8; c < cols; c += 512) {
+      const uint4 w = *reinterpret_cast<const uint4*>(p + c);
+      const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+      float t = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t += from_bf16((uint16_t)(q[k] & 0xFFFFu)) + from_bf16((uint16_t)(q[k] >> 16));
+      s += t;
+    }
+  } else {
+    for (int64_t c = lane; c < cols; c += 64) s += from_bf16(p[c]);
+  }
   s = wave_sum_d(s);
   if (lane == 0) out[row] = (float)s;
 }
@@ -525,21 +609,40 @@ hipError_t set_vit_smem_limit(int D, int T) {
     if (e == hipSuccess && bytes > 64 * 1024)
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   };
-  set(reinterpret_cast<const void*>(k_ln_fwd), ln);
-  set(reinterpret_cast<const void*>(k_ln_bwd), ln);
+  set(reinterpret_cast<const void*>(k_ln_fwd<4, 1>), ln);
+  set(reinterpret_cast<const void*>(k_ln_fwd<4, 2>), ln);
+  set(reinterpret_cast<const void*>(k_ln_fwd<4, 4>), ln);
+  set(reinterpret_cast<const void*>(k_ln_fwd<4, 8>), ln);
+  set(reinterpret_cast<const void*>(k_ln_fwd<1, 32>), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd<4, 1>), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd<4, 2>), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd<4, 4>), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd<4, 8>), ln);
+  set(reinterpret_cast<const void*>(k_ln_bwd<1, 32>), ln);
   set(reinterpret_cast<const void*>(k_attn_softmax), rows);
   set(reinterpret_cast<const void*>(k_attn_ds), rows);
   return e;
 }
+
+// LayerNorm kernels: V = 4 with J = D / 256 for the usual widths, else V = 1 up to 2048.
+#define VIT_LN_DISPATCH(KERN, ...)                                                             \
+  if (D % 256 == 0 && D / 256 == 1) return go(KERN<4, 1>, __VA_ARGS__);                       \
+  if (D % 256 == 0 && D / 256 == 2) return go(KERN<4, 2>, __VA_ARGS__);                       \
+  if (D % 256 == 0 && D / 256 == 4) return go(KERN<4, 4>, __VA_ARGS__);                       \
+  if (D % 256 == 0 && D / 256 == 8) return go(KERN<4, 8>, __VA_ARGS__);                       \
+  return go(KERN<1, 32>, __VA_ARGS__);
 
 hipError_t launch_ln_fwd(const float* x, int64_t rows, int D, const float* gamma,
                          const float* beta, uint16_t* y, uint16_t* yt, int64_t ld_t,
                          float* mean, float* rstd, hipStream_t s) {
   if (rows % kRows != 0 || D % 64 != 0 || D > 2048) return hipErrorInvalidValue;
   const size_t shm = yt ? (size_t)kRows * (D + 2) * 2 : 0;
-  hipLaunchKernelGGL(k_ln_fwd, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, x, D, gamma,
-                     beta, y, yt, ld_t, mean, rstd);
-  return hipGetLastError();
+  auto go = [&](auto kern, int) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, x, D, gamma,
+                       beta, y, yt, ld_t, mean, rstd);
+    return hipGetLastError();
+  };
+  VIT_LN_DISPATCH(k_ln_fwd, 0)
 }
 
 hipError_t launch_ln_bwd(const float* dy, const float* x, const float* mean, const float* rstd,
@@ -548,9 +651,12 @@ hipError_t launch_ln_bwd(const float* dy, const float* x, const float* mean, con
                          float* pb, hipStream_t s) {
   if (rows % kRows != 0 || D % 64 != 0 || D > 2048) return hipErrorInvalidValue;
   const size_t shm = res16t ? (size_t)kRows * (D + 2) * 2 : 0;
-  hipLaunchKernelGGL(k_ln_bwd, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, dy, x, mean,
-                     rstd, gamma, D, dres, res16, res16t, ld_t, pg, pb);
-  return hipGetLastError();
+  auto go = [&](auto kern, int) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, dy, x, mean,
+                       rstd, gamma, D, dres, res16, res16t, ld_t, pg, pb);
+    return hipGetLastError();
+  };
+  VIT_LN_DISPATCH(k_ln_bwd, 0)
 }
 
 hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out, bool accumulate,
