@@ -342,7 +342,8 @@ hipError_t weight_grad(ensf_vit* v, const Lin& l, const uint16_t* dyt, const uin
   while (splits > 1 && Ta / splits < 256) --splits;
   hipError_t e;
   if (splits > 1) {
-    g.kchunk = (Ta / splits + 31) / 32 * 32;
+    const int64_t q = Ta % 64 == 0 ? 64 : 32;   // the k-step of the larger tiles divides it
+    g.kchunk = (Ta / splits + q - 1) / q * q;
     splits = (int)((Ta + g.kchunk - 1) / g.kchunk);
     g.splits = splits;
     g.part_stride = (int64_t)l.out * l.in;

@@ -44,10 +44,25 @@ struct VGemm {
   // [s * kchunk, (s + 1) * kchunk), writes its partial product to f32 + s * part_stride
   int64_t kchunk, part_stride;
   int splits;
+  int tile;   // VTile; kTileAuto chooses by shape
 };
 
-// Tile shape for an M x N product: 128 x 128 (four waves of 64 x 64), 64 x 64 or 32 x 32;
-// M and N must be multiples of the chosen tile, K of 32 (and kchunk, when split, of 32).
+// Tile shapes (rows x columns of C, k-step, LDS stages), four waves unless noted.  Measured on
+// the 64^2 Table II products: 256 x 128 and 256 x 256 tiles were slower than these.
+enum VTile : int {
+  kTileAuto = 0,
+  kTile128 = 1,         // 128 x 128, waves of 64 x 64, k-step 64, one stage
+  kTile128pp = 2,       // 128 x 128, k-step 64, two stages
+  kTile64 = 3,          // 64 x 64, waves of 32 x 32, k-step 32, two stages
+  kTile32 = 4,          // 32 x 32 on one wave, k-step 32
+  kNumTiles = 5
+};
+
+// M and N must be multiples of the chosen tile, K (and kchunk, when split) of its k-step.
+// Automatic choice by the contraction length per workgroup (kchunk when split): up to 256
+// (attention, patch embedding) 64 x 64 tiles, whose short k loops need the extra
+// workgroups; otherwise 128 x 128 where K is a multiple of 64 (two stages from 4096 on),
+// else 64 x 64, else 32 x 32.
 hipError_t launch_vgemm(const VGemm& g, int batch, hipStream_t s);
 
 // rows x D FP32 -> LayerNorm (population variance, eps 1e-5) -> BF16 rows y (ld D) and,

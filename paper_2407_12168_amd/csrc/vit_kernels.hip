@@ -71,11 +71,13 @@ __device__ __forceinline__ void store_tile_transposed(const uint16_t* tile, int 
 
 // Four-wave tiles are compiled for three resident waves per SIMD (three workgroups per CU,
 // whose LDS stages also fit): the register budget that leaves is enough without spills.
-template <int WGM, int WGN, int TM, int TN>
-__global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1) void k_vgemm(VGemm g) {
-  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32, BK = 32;
+// BK is the k-step, ST the LDS stage count (2: ping-pong when both stages fit).
+template <int WGM, int WGN, int TM, int TN, int BK, int ST>
+__global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1)
+void k_vgemm(VGemm g) {
+  constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
   using S = TileSmem<kBF16, BM, BN, BK, false>;
-  constexpr bool PP = 2 * S::kBytes <= kPingPongBytes;
+  constexpr bool PP = ST == 2 && 2 * S::kBytes <= kPingPongBytes;
   __shared__ __attribute__((aligned(16))) char smem[PP ? 2 * S::kBytes : S::kBytes];
 
   const int ntiles = (int)(gridDim.x / g.splits);
@@ -589,17 +591,31 @@ hipError_t launch_vgemm(const VGemm& g0, int batch, hipStream_t s) {
   if (g.splits < 1) g.splits = 1;
   if (g.splits > 1 && (g.kchunk % 32 != 0 || g.kchunk * g.splits < g.K || batch != 1))
     return hipErrorInvalidValue;
-  auto go = [&](auto kern, int bm, int bn, int threads) {
+  auto go = [&](auto kern, int bm, int bn, int bk, int threads) {
+    if (g.M % bm || g.N % bn || g.K % bk || (g.splits > 1 && g.kchunk % bk))
+      return hipErrorInvalidValue;
     g.tiles_n = g.N / bn;
     hipLaunchKernelGGL(kern, dim3((unsigned)((g.M / bm) * (g.N / bn) * g.splits),
                                   (unsigned)batch),
                        dim3(threads), 0, s, g);
     return hipGetLastError();
   };
-  if (g.M % 128 == 0 && g.N % 128 == 0) return go(k_vgemm<2, 2, 2, 2>, 128, 128, 256);
-  if (g.M % 64 == 0 && g.N % 64 == 0) return go(k_vgemm<2, 2, 1, 1>, 64, 64, 256);
-  if (g.M % 32 == 0 && g.N % 32 == 0) return go(k_vgemm<1, 1, 1, 1>, 32, 32, 64);
-  return hipErrorInvalidValue;
+  int tile = g.tile;
+  if (tile == kTileAuto) {
+    const int64_t keff = g.splits > 1 ? g.kchunk : g.K;
+    const bool m128 = g.M % 128 == 0 && g.N % 128 == 0, m64 = g.M % 64 == 0 && g.N % 64 == 0;
+    if (keff <= 256 && m64) tile = kTile64;
+    else if (m128 && keff % 64 == 0) tile = keff >= 4096 ? kTile128pp : kTile128;
+    else if (m64) tile = kTile64;
+    else tile = kTile32;
+  }
+  switch (tile) {
+    case kTile128: return go(k_vgemm<2, 2, 2, 2, 64, 1>, 128, 128, 64, 256);
+    case kTile128pp: return go(k_vgemm<2, 2, 2, 2, 64, 2>, 128, 128, 64, 256);
+    case kTile64: return go(k_vgemm<2, 2, 1, 1, 32, 2>, 64, 64, 32, 256);
+    case kTile32: return go(k_vgemm<1, 1, 1, 1, 32, 2>, 32, 32, 32, 64);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t set_vit_smem_limit(int D, int T) {
