@@ -120,7 +120,7 @@ def run_vit_bench(a):
     embed 1024, MLP ratio 4) on synthetic 2 x 64 x 64 states, as matrix-product TFLOP/s."""
     import torch
 
-    from paper_2407_12168_amd import vit
+    from paper_2407_12168_amd import ensf, vit
     dev = torch.device("cuda:0")
     B = a.vit_batch
     g = torch.Generator(device="cpu").manual_seed(2407)
@@ -142,6 +142,7 @@ def run_vit_bench(a):
     m.destroy()
     flops = vit_training_flops(12, 256, 1024, 4096, 32, B)
     tf = flops / (ms * 1e-3) / 1e12
+    rate = ensf.ensf_measure_mfma_rate("bf16")
     line = {
         "metric": "ViT surrogate training TFLOP/s (matrix products)", "value": tf,
         "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -151,7 +152,9 @@ def run_vit_bench(a):
                                f"MLP 4096 ({n_params} parameters), batch {B}, forward + "
                                f"backward + Adam", "batch": B, "params": n_params},
         "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None,
+                     "mfma_rate_measured": round(rate, 1),
+                     "frac_of_measured_rate": round(tf / rate, 4)},
         "flops_per_step": flops, "final_loss": loss,
     }
     print(json.dumps(line), flush=True)
@@ -207,7 +210,7 @@ def run_form(probs, precision, steps, warmup, dev, lik_step="explicit", wx_spars
     return ms, [m / n_launch for m in phase_ms]
 
 
-def roofline(probs, precision, phase_avg_ms, config=None, wx_sparse=False):
+def roofline(probs, precision, phase_avg_ms, config=None, wx_sparse=False, mfma_rate=None):
     # algorithmic flops per launch: Gram = sum 2*M_p*N*d, W.X the same (split forms issue 3x).
     # With the degenerate-weight W.X most of its tiles are gathers, not contractions, so the
     # Gram is the kernel priced against the MFMA peak.
@@ -229,6 +232,12 @@ def roofline(probs, precision, phase_avg_ms, config=None, wx_sparse=False):
         out["frac_issued_per_kernel"] = {
             n: round(3 * flops / (phase_avg_ms[i] * 1e-3) / 1e12 / peak, 4)
             for i, n in ((0, "k_gram"), (2, "k_wx"))}
+    if mfma_rate:
+        # the same work against the matrix-core rate this card sustains (ensf_measure_mfma_rate:
+        # register-only MFMA chains under its own clock and power limits)
+        issued = 3 * achieved if precision == "bf16x3" else achieved
+        out["mfma_rate_measured"] = round(mfma_rate, 1)
+        out["frac_of_measured_rate"] = round(issued / mfma_rate, 4)
     return out
 
 
@@ -310,6 +319,7 @@ def main():
     import torch
 
     import workloads
+    from paper_2407_12168_amd import ensf
     dev = torch.device("cuda:0")
     if a.config == 4:
         probs = workloads.batched_problems(n_filters=64, n_steps=100, sigma_o=0.05)
@@ -341,6 +351,8 @@ def main():
                                     zip(("k_gram", "k_softmax", "k_wx"), phase3)},
                    "note": "same analysis; W.X tiles whose weight rows have at most 8 weights "
                            ">= 2^-30 gather xhat from those members (dense tiles otherwise)"}
+    # after the timed runs: the attainable MFMA rate of each form's instruction on this card
+    rates = {pr: ensf.ensf_measure_mfma_rate(pr) for pr in {a.precision, other} - {"none"}}
     ndk = sum(p.n_members * p.dim * p.n_steps for p in probs)
     p0 = probs[0]
     cfg = {"workload": WORKLOAD[a.config], "precision": a.precision}
@@ -363,12 +375,13 @@ def main():
         "dtype": "f32" if a.precision == "fp32" else a.precision,
         "data": "synthetic",
         "config": cfg,
-        "roofline": roofline(probs, a.precision, phase, a.config, a.wx_sparse),
+        "roofline": roofline(probs, a.precision, phase, a.config, a.wx_sparse,
+                             rates.get(a.precision)),
     }
     if other != "none":
         line["forms"] = {other: {"value": ndk / (ms2 * 1e-3), "ms_per_step": ms2,
                                  "roofline": roofline(probs, other, phase2, a.config,
-                                                      a.wx_sparse)},
+                                                      a.wx_sparse, rates.get(other))},
                          "speedup_bf16x3_over_fp32":
                              (ms / ms2) if a.precision == "fp32" else (ms2 / ms)}
     if variant is not None:

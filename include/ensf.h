@@ -206,6 +206,18 @@ ensf_status ensf_autotune_batched(ensf_ctx* ctx, const ensf_problem* probs, int3
 ensf_status ensf_profile_phases(ensf_ctx* ctx, int32_t enable);
 ensf_status ensf_phase_times(ensf_ctx* ctx, double* ms, int64_t* count);
 
+/* Measures the attainable matrix-core rate of the current device for a form's MFMA
+   (v_mfma_f32_32x32x2f32 for ENSF_PREC_FP32, v_mfma_f32_32x32x16_bf16 otherwise): 2048
+   workgroups of four waves, each wave eight independent accumulator chains on register
+   operands, timed with HIP events on the stream over 100 back-to-back launches (about 0.1 s)
+   after 20 warm-up launches.  This is the throughput the card sustains under its own clock
+   and power limits, the
+   ceiling for the analysis kernels' issued MFMA work beside the published peak (Sec. IV-B
+   reports the analysis against the hardware it ran on).  *tflops receives TFLOP/s (dense,
+   2 flops per multiply-add).  Allocates and frees 2 MiB of device memory; synchronises the
+   stream.  Errors: ENSF_EINVAL (tflops NULL, bad precision), ENSF_EHIP. */
+ensf_status ensf_measure_mfma_rate(int32_t precision, double* tflops, void* stream);
+
 /* Size in bytes of the device buffer behind ensf_analysis_noalloc: one statically allocated
    array in the library's device code, held by every GPU the entry point runs on until the
    process ends. */

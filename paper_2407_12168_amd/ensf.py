@@ -53,7 +53,7 @@ EXPORTS = ("ensf_default_options", "ensf_create", "ensf_analysis", "ensf_analysi
            "ensf_score", "ensf_rng_normal", "ensf_ensemble_stats", "ensf_sync_status",
            "ensf_autotune", "ensf_autotune_batched", "ensf_profile_phases", "ensf_phase_times",
            "ensf_destroy", "ensf_status_string", "ensf_last_error_string",
-           "ensf_analysis_noalloc")
+           "ensf_analysis_noalloc", "ensf_measure_mfma_rate")
 
 
 def _lib():
@@ -83,6 +83,7 @@ def _lib():
         L.ensf_destroy.argtypes = [vp]
         L.ensf_analysis_noalloc.argtypes = [ctypes.POINTER(ensf_options), vp, i32, i64, vp, i32,
                                             vp, vp, i64, ctypes.c_float, i32, u64, u32, vp, vp]
+        L.ensf_measure_mfma_rate.argtypes = [i32, ctypes.POINTER(ctypes.c_double), vp]
         L.ensf_status_string.argtypes = [ctypes.c_int]
         L.ensf_status_string.restype = ctypes.c_char_p
         L.ensf_last_error_string.argtypes = []
@@ -268,6 +269,14 @@ def ensf_phase_times(ctx):
     n = ctypes.c_int64(0)
     _check(_lib().ensf_phase_times(ctx, ms, ctypes.byref(n)), "ensf_phase_times")
     return tuple(ms), n.value
+
+
+def ensf_measure_mfma_rate(precision="bf16x3", stream=None):
+    """Attainable dense MFMA TFLOP/s of the current device for a form's matrix instruction."""
+    out = ctypes.c_double(0.0)
+    _check(_lib().ensf_measure_mfma_rate(PRECISIONS[precision], ctypes.byref(out),
+                                         _stream(stream)), "ensf_measure_mfma_rate")
+    return out.value
 
 
 def ensf_destroy(ctx):
