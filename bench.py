@@ -31,7 +31,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # calibrated with a plain copy of known size (profiles/hbm_traffic_*.md);
 # keyed by (workload config, precision, kernel).  Absent entries are reported as null.
-MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 105.66e6, (2, "bf16x3", "k_wx"): 105.09e6,
+MEASURED_TRAFFIC = {(2, "fp32", "k_wx"): 103.32e6, (2, "bf16x3", "k_wx"): 103.32e6,
                     (3, "fp32", "k_wx"): 2620.9e6, (3, "bf16x3", "k_wx"): 2645.9e6}
 WORKLOAD = {
     1: "EnSF analysis d=2x64x64=8192, N=M_p=20, arctan obs of all components, sigma_o=0.05, K=100",
