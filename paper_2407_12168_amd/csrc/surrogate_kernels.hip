@@ -94,6 +94,35 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
           *reinterpret_cast<const u32x4*>(src + (int64_t)xs * CIN + c8 * 8);
     }
   };
+  // The next input row is fetched into registers before a row's MFMAs and written to its
+  // ring slot after them, so its memory latency overlaps the compute (rows of up to
+  // kPf * 256 16-byte vectors; longer rows are loaded after the compute instead).
+  constexpr int kPf = 8;
+  const int row_vecs = (W + 2) * (CIN / 8);
+  const bool prefetch = row_vecs <= kPf * 256;
+  u32x4 pf[kPf];
+  auto fetch_row = [&](int yy) {
+    const uint16_t* src = in + (int64_t)wrap(yy, H) * W * CIN;
+#pragma unroll
+    for (int k = 0; k < kPf; ++k) {
+      const int v = tid + k * 256;
+      if (v < row_vecs) {
+        const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
+        pf[k] = *reinterpret_cast<const u32x4*>(src + (int64_t)wrap(xh - 1, W) * CIN + c8 * 8);
+      }
+    }
+  };
+  auto commit_row = [&](int yy) {
+    uint16_t* dst = sIn + wrap(yy, 3) * row_elems;
+#pragma unroll
+    for (int k = 0; k < kPf; ++k) {
+      const int v = tid + k * 256;
+      if (v < row_vecs) {
+        const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
+        *reinterpret_cast<u32x4*>(dst + xh * LDI + c8 * 8) = pf[k];
+      }
+    }
+  };
   load_row(y0 - 1);
   load_row(y0);
   load_row(y0 + 1);
@@ -101,6 +130,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
 
   float loss_local = 0.0f;
   for (int y = y0; y < y1; ++y) {
+    if (prefetch && y + 1 < y1) fetch_row(y + 2);
     for (int g = wave; g < W / 32; g += 4) {
       f32x16_t acc[TN];
 #pragma unroll
@@ -158,7 +188,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
     }
     __syncthreads();                      // all reads of row y-1's slot are done
     if (y + 1 < y1) {
-      load_row(y + 2);
+      if (prefetch) commit_row(y + 2); else load_row(y + 2);
       __syncthreads();
     }
   }
@@ -200,19 +230,37 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
   const bool active = wave < WM * WN;
   const int wm = wave / WN, wn = wave % WN;
 
-  // staging unit of this thread: pixel pair pp, channel octet c8
-  auto stage = [&](uint16_t* dst, int C, auto src_of, int64_t pb) {
-    for (int v = tid; v < (KS / 2) * (C / 8); v += 256) {
+  // staging unit of this thread: pixel pair pp, channel octet c8.  A k-step's units are
+  // fetched into registers (fetch) one k-step ahead and written to LDS (put) after the
+  // previous k-step's MFMAs, so the loads overlap them.
+  constexpr int kNA = (KS / 2) * (COUT / 8), kNB = (KS / 2) * (CIN / 8);   // units per step
+  constexpr int kUA = (kNA + 255) / 256, kUB = (kNB + 255) / 256;
+  struct Units {
+    u32x4 a0[kUA], a1[kUA], b0[kUB], b1[kUB];
+  } u;
+  auto fetch_op = [&](u32x4* w0s, u32x4* w1s, int n, int total, auto src_of, int64_t pb) {
+    for (int k = 0; k < n; ++k) {
+      const int v = tid + k * 256;
+      if (v >= total) break;
       const int pp = v % (KS / 2), c8 = v / (KS / 2);
       u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
       const int64_t p = pb + 2 * pp;
       if (p < p1) w0 = *reinterpret_cast<const u32x4*>(src_of(p) + c8 * 8);
       if (p + 1 < p1) w1 = *reinterpret_cast<const u32x4*>(src_of(p + 1) + c8 * 8);
+      w0s[k] = w0;
+      w1s[k] = w1;
+    }
+  };
+  auto put_op = [&](uint16_t* dst, const u32x4* w0s, const u32x4* w1s, int n, int total) {
+    for (int k = 0; k < n; ++k) {
+      const int v = tid + k * 256;
+      if (v >= total) break;
+      const int pp = v % (KS / 2), c8 = v / (KS / 2);
       uint32_t* d = reinterpret_cast<uint32_t*>(dst + (c8 * 8) * LDK + 2 * pp);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        d[(2 * q) * (LDK / 2)] = (w0[q] & 0xFFFFu) | (w1[q] << 16);
-        d[(2 * q + 1) * (LDK / 2)] = (w0[q] >> 16) | (w1[q] & 0xFFFF0000u);
+        d[(2 * q) * (LDK / 2)] = (w0s[k][q] & 0xFFFFu) | (w1s[k][q] << 16);
+        d[(2 * q + 1) * (LDK / 2)] = (w0s[k][q] >> 16) | (w1s[k][q] & 0xFFFF0000u);
       }
     }
   };
@@ -227,11 +275,17 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
+  auto fetch = [&](int64_t pb) {
+    fetch_op(u.a0, u.a1, kUA, kNA, du_row, pb);
+    fetch_op(u.b0, u.b1, kUB, kNB, in_row, pb);
+  };
+  if (p0 < p1) fetch(p0);
   for (int64_t pb = p0; pb < p1; pb += KS) {
     __syncthreads();
-    stage(sA, COUT, du_row, pb);
-    stage(sB, CIN, in_row, pb);
+    put_op(sA, u.a0, u.a1, kUA, kNA);
+    put_op(sB, u.b0, u.b1, kUB, kNB);
     __syncthreads();
+    if (pb + KS < p1) fetch(pb + KS);
     if (active) {
 #pragma unroll
       for (int kk = 0; kk < KS; kk += 16) {
