@@ -103,6 +103,61 @@ def run_cycle_bench(a):
     print(json.dumps(line), flush=True)
 
 
+def run_vit_cycle_bench(a):
+    """The Table II 64^2 ViT surrogate as the cycle's forecast model: trained on SQG pairs by
+    the library's kernels, then cycled against the truth with the SQG forecast, with no
+    forecast model, with the ViT, and with the ViT trained online on the observations; the
+    metric is the analyses' member-dim updates per second of the ViT cycle."""
+    import numpy as np
+    import torch
+
+    from paper_2407_12168_amd import cycle
+    dev = torch.device("cuda:0")
+    cfg = cycle.CycleConfig(grid=64, members=256, cycles=a.cycles, pseudo_steps=400,
+                            sqg_dt=0.025, steps_per_cycle=10, spinup_steps=800)
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)
+    x, y = cycle.training_pairs(2000, cfg, dev)
+    xv, yv = cycle.training_pairs(64, cfg, dev, seed=cfg.seed + 77, perturbed=0.0)
+    t0 = time.perf_counter()
+    net, hist = cycle.train_vit(x, y, epochs=a.epochs, batch=32, lr=5e-5, val=(xv, yv),
+                                log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del x, y
+    online = cycle.OnlineTuning(steps=2, lr=3e-6, window=8)
+    runs = {}
+    for name, fc, kw in (("sqg", "sqg", {}), ("persistence", "persistence", {}),
+                         ("vit", "vit", {"surrogate": net}),
+                         ("vit_online", "vit", {"surrogate": net, "online": online})):
+        runs[name] = cycle.run_cycle(cfg, fc, dev=dev, log=log, **kw)
+    net.destroy()
+    r = runs["vit"]
+    ndk = cfg.members * 2 * cfg.grid * cfg.grid * cfg.pseudo_steps
+    ms = 1e3 * float(np.mean(r.analysis_s))
+    first = min(5, cfg.cycles - 1)
+    line = {
+        "metric": "EnSF member-dim updates/s (N*d*K/s)",
+        "value": ndk / (ms * 1e-3), "unit": "member-dim updates/s",
+        "n_gpus": 1, "steps": cfg.cycles, "warmup": 0, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"ViT-forecast assimilation cycle: {cfg.cycles} cycles on "
+                               f"2x64x64 SQG states, N=M_p={cfg.members}, forecast by the "
+                               f"Table II 64x64 ViT (151M parameters) trained on 2000 SQG "
+                               f"pairs for {a.epochs} epochs, obs every 4th point, "
+                               f"sigma_o=0.05, K=400", "members": cfg.members,
+                   "dim": 2 * cfg.grid * cfg.grid, "pseudo_steps": cfg.pseudo_steps},
+        "cycle": {n: {"rmse_analysis_mean": float(np.mean(v.rmse[first:])),
+                      "rmse_forecast_mean": float(np.mean(v.rmse_forecast[first:])),
+                      "forecast_ms_per_cycle": 1e3 * float(np.mean(v.forecast_s)),
+                      "analysis_ms_per_cycle": 1e3 * float(np.mean(v.analysis_s))}
+                  for n, v in runs.items()},
+        "vit_training": {"seconds": train_s, "final_val_mse": hist[-1]["val_mse"],
+                         "persistence_val_mse": float(torch.mean((xv - yv) ** 2))},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def vit_training_flops(layers, tokens, embed, mlp_hidden, patch_dim, batch):
     """Matrix-product flops of one ViT training step (2 per multiply-add): forward, and the
     weight gradients of every linear layer plus the input gradients of all but the patch
@@ -303,6 +358,9 @@ def main():
     ap.add_argument("--vit", action="store_true",
                     help="time the Table II 64x64 ViT surrogate's training step instead")
     ap.add_argument("--vit-batch", type=int, default=32)
+    ap.add_argument("--vit-cycle", action="store_true",
+                    help="cycle with the Table II ViT as the forecast model (2x64x64 SQG; "
+                         "--cycles, --epochs apply)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: runs on one GPU only (the analysis would shard over particles or "
@@ -311,6 +369,9 @@ def main():
 
     if a.vit:
         run_vit_bench(a)
+        return
+    if a.vit_cycle:
+        run_vit_cycle_bench(a)
         return
     if a.config == 5:
         run_cycle_bench(a)

@@ -2,9 +2,10 @@
 Sec. IV-A): forecast every member, observe the truth, run the EnSF analysis, repeat.
 
 Everything runs on the GPU through libensf: the truth and the physics forecast are the
-FP64 SQG model (ensf_sqg), the learned forecast is the conv surrogate (ensf_surrogate),
-the analysis is ensf_analysis.  Host code only draws the synthetic observation noise and
-the initial ensemble and orchestrates the calls.
+FP64 SQG model (ensf_sqg), the learned forecast is the conv surrogate (ensf_surrogate) or
+the ViT surrogate (ensf_vit, Sec. III-B), the analysis is ensf_analysis.  A learned forecast
+can keep training online on the cycle's own analyses (Sec. I, Sec. V).  Host code only draws
+the synthetic observation noise and the initial ensemble and orchestrates the calls.
 """
 import time
 from dataclasses import dataclass, field
@@ -40,6 +41,20 @@ class CycleConfig:
     perturb_white: float = 0.1
     seed: int = 2412
     filter_seed: int = 12173
+
+
+@dataclass
+class OnlineTuning:
+    """Online training of the learned forecast on observations during the cycle (the paper
+    adapts the surrogate with observational data, Sec. I and V).  The loss is the forecast's
+    misfit at the observed components only: for each of the latest `window` cycles the input
+    is the previous analysis mean x and the target is the network's own forecast f(x) with
+    the observed components replaced by that cycle's observations, so the squared error (and
+    its gradient) lives on the observed components.  After each analysis the surrogate takes
+    `steps` Adam steps at rate `lr`.  Needs the identity observation operator."""
+    steps: int = 2
+    lr: float = 1e-5
+    window: int = 8
 
 
 @dataclass
@@ -82,14 +97,35 @@ def climate_trajectories(sqg, cfg, samples, rng, dev, n_traj=None):
     return out
 
 
-def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
-    """forecast: "sqg" (the physics model, which is also the truth's model), "conv" (the
-    trained surrogate) or "persistence" (no forecast model: the analysis is carried over)."""
+def _surrogate_ops(forecast, surrogate):
+    """(forward(x, y), train_step(x, target, lr)) of a learned forecast model."""
+    if forecast == "conv":
+        from .surrogate import ensf_surrogate_forward, ensf_surrogate_train_step
+        return (lambda x, y: ensf_surrogate_forward(surrogate.handle, x, y),
+                lambda x, t, lr: ensf_surrogate_train_step(surrogate.handle, x, t, lr,
+                                                           want_loss=False))
+    if forecast == "vit":
+        from .vit import ensf_vit_forward, ensf_vit_train_step
+        return (lambda x, y: ensf_vit_forward(surrogate.handle, x, y),
+                lambda x, t, lr: ensf_vit_train_step(surrogate.handle, x, t, lr, want_loss=False))
+    return None, None
+
+
+def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None, online=None):
+    """forecast: "sqg" (the physics model, which is also the truth's model), "conv" or "vit"
+    (a trained surrogate) or "persistence" (no forecast model: the analysis is carried over).
+    online: an OnlineTuning to keep training a learned forecast on the analyses."""
     import torch
 
     from . import ensf
-    from .surrogate import ensf_surrogate_forward
 
+    if forecast not in ("sqg", "conv", "vit", "persistence"):
+        raise ValueError(forecast)
+    net_forward, net_train = _surrogate_ops(forecast, surrogate)
+    if online is not None and net_train is None:
+        raise ValueError("online training needs a learned forecast")
+    if online is not None and cfg.obs_op != "linear":
+        raise ValueError("online training on observations needs obs_op='linear'")
     dev = dev or torch.device("cuda:0")
     rng = np.random.default_rng(cfg.seed)
     n = cfg.grid
@@ -105,16 +141,22 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
         idx = torch.from_numpy(obs_indices(n, cfg.obs_stride)).to(dev)
         ctx = ensf.Context(precision=cfg.precision, obs_op=cfg.obs_op,
                            spread_relax=cfg.spread_relax)
+        fc_out = torch.empty_like(ens) if forecast == "vit" else None
+        pairs = []
         try:
             for c in range(cfg.cycles):
                 sqg.run(truth, truth, cfg.steps_per_cycle)
                 torch.cuda.synchronize()
+                prev_mean = ens.mean(0).view(1, 2, n, n).clone() if online is not None else None
                 t0 = time.perf_counter()
                 states = ens.view(cfg.members, 2, n, n)
                 if forecast == "sqg":
                     sqg.run(states, states, cfg.steps_per_cycle)
                 elif forecast == "conv":
-                    ensf_surrogate_forward(surrogate.handle, states, states)
+                    net_forward(states, states)
+                elif forecast == "vit":   # output may not alias the input
+                    net_forward(states, fc_out.view(states.shape))
+                    ens.copy_(fc_out)
                 elif forecast != "persistence":
                     raise ValueError(forecast)
                 torch.cuda.synchronize()
@@ -138,6 +180,17 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None):
                 res.rmse_forecast_obs.append(float(torch.sqrt(torch.mean(
                     (post.mean(0)[idx.long()] - tv[idx.long()]) ** 2))))
                 res.spread.append(float(torch.sqrt(torch.mean(ens.var(0)))))
+                if online is not None:
+                    pairs = (pairs + [(prev_mean, y)])[-online.window:]
+                    xs = torch.cat([p[0] for p in pairs]).contiguous()
+                    ys = torch.stack([p[1] for p in pairs])
+                    li = idx.long()
+                    for _ in range(online.steps):
+                        ts = torch.empty_like(xs)
+                        net_forward(xs, ts)
+                        tv_ = ts.view(len(pairs), -1)
+                        tv_[:, li] = ys
+                        net_train(xs, ts, online.lr)
                 if log:
                     log(f"cycle {c}: forecast rmse {res.rmse_forecast[-1]:.4f}, analysis rmse "
                         f"{res.rmse[-1]:.4f}, spread {res.spread[-1]:.4f}, forecast "
@@ -181,6 +234,42 @@ def training_pairs(count, cfg, dev, seed=None, perturbed=None):
     if not (bool(torch.isfinite(x).all()) and bool(torch.isfinite(y).all())):
         raise RuntimeError("SQG trajectory became non-finite (reduce sqg_dt)")
     return x.float().contiguous(), y.float().contiguous()
+
+
+def train_vit(x, y, epochs=20, batch=32, lr=1e-4, seed=0, log=None, val=None, **arch):
+    """Trains a ViT surrogate (Sec. III-B; architecture keywords as vit.ViT, default the
+    Table II 64^2 model) on pairs (x, y) with the library's Adam; returns it and the
+    per-epoch history (as train_surrogate)."""
+    import torch
+
+    from .vit import ViT, ensf_vit_forward, ensf_vit_train_step
+    n = x.shape[0]
+    a = dict(patch=4, layers=12, heads=8, embed=1024, mlp_hidden=4096)
+    a.update(arch)
+    net = ViT(channels=x.shape[1], height=x.shape[2], width=x.shape[3], max_batch=batch,
+              seed=seed, **a)
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(x.device)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            sel = perm[b0:b0 + batch]
+            loss = ensf_vit_train_step(net.handle, x[sel].contiguous(), y[sel].contiguous(), lr,
+                                       want_loss=(b0 == 0))
+            if loss is not None:
+                tot += loss
+                cnt += 1
+        entry = {"epoch": ep, "train_loss_first_batch": tot / max(cnt, 1)}
+        if val is not None:
+            xv, yv = val
+            pred = torch.empty_like(xv)
+            ensf_vit_forward(net.handle, xv, pred)
+            entry["val_mse"] = float(torch.mean((pred - yv) ** 2))
+        hist.append(entry)
+        if log:
+            log(str(entry))
+    return net, hist
 
 
 def train_surrogate(x, y, epochs=30, batch=32, lr=1e-3, seed=0, log=None, val=None):

@@ -45,3 +45,17 @@ def test_roofline_prices_the_dominant_kernel():
     r = b.roofline([p, q], "fp32", [0.010, 0.001, 0.020], config=4)
     want = (flops + 2.0 * 64 * 64 * 8192) / 0.020e-3 / 1e12
     assert r["achieved"] == pytest.approx(want, rel=1e-3) and r["traffic"] is None
+
+
+def test_cycle_rejects_online_training_without_a_learned_forecast():
+    from paper_2407_12168_amd import cycle
+    cfg = cycle.CycleConfig(grid=32, members=8, cycles=1)
+    with pytest.raises(ValueError):
+        cycle.run_cycle(cfg, "sqg", online=cycle.OnlineTuning())
+    with pytest.raises(ValueError):
+        cycle.run_cycle(cfg, "persistence", online=cycle.OnlineTuning())
+    with pytest.raises(ValueError):
+        cycle.run_cycle(cycle.CycleConfig(obs_op="arctan"), "conv", surrogate=object(),
+                        online=cycle.OnlineTuning())
+    with pytest.raises(ValueError):
+        cycle.run_cycle(cfg, "spectral")

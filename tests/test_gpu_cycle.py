@@ -1,5 +1,6 @@
 """Assimilation cycle on the GPU (reduced size): truth and physics forecast by the SQG
-model, learned forecast by the trained conv surrogate, split-BF16 EnSF analysis.
+model, learned forecast by the trained conv surrogate or a ViT surrogate, split-BF16 EnSF
+analysis.
 
 Checks: the cycle stays finite and bounded; at the observed components the analysis
 error is below the forecast error every cycle; the trained network is a useful forecast
@@ -60,3 +61,32 @@ def test_trained_surrogate_beats_no_forecast_and_tracks_physics(dev):
     # forecast cannot beat it on accuracy; it must keep the analysis within a factor of it
     # (the full-size cycle measures 0.88x: the network forecast is also smoother)
     assert m(conv) < CONV_VS_SPECTRAL * m(phys)
+
+
+# a reduced ViT (the Table II architecture with 4 layers of width 256) keeps the test short;
+# the Table II model itself runs in `bench.py --vit-cycle`
+VIT_ARCH = dict(patch=4, layers=4, heads=4, embed=256, mlp_hidden=1024)
+VIT_CFG = cycle.CycleConfig(grid=64, members=64, cycles=12, pseudo_steps=400, sqg_dt=0.025,
+                            steps_per_cycle=10, spinup_steps=800)
+
+
+def test_vit_forecast_cycle_and_online_training(dev):
+    """The ViT surrogate, trained on SQG pairs by the library's kernels, is a usable forecast
+    model (better than persistence on validation pairs and in the cycle), and online training
+    on the observations (OnlineTuning) keeps the cycle finite and bounded."""
+    x, y = cycle.training_pairs(1024, VIT_CFG, dev)
+    xv, yv = cycle.training_pairs(64, VIT_CFG, dev, seed=99, perturbed=0.0)
+    base = float(torch.mean((xv - yv) ** 2))
+    net, hist = cycle.train_vit(x, y, epochs=20, batch=32, lr=3e-4, val=(xv, yv), **VIT_ARCH)
+    print(f"validation mse: persistence {base:.4e}, ViT {hist[-1]['val_mse']:.4e}")
+    assert hist[-1]["val_mse"] < base
+    f = lambda r: float(np.mean(r.rmse_forecast[2:]))
+    vitr = cycle.run_cycle(VIT_CFG, "vit", surrogate=net, dev=dev)
+    pers = cycle.run_cycle(VIT_CFG, "persistence", dev=dev)
+    onl = cycle.run_cycle(VIT_CFG, "vit", surrogate=net, dev=dev,
+                          online=cycle.OnlineTuning(steps=2, lr=3e-6, window=4))
+    net.destroy()
+    print(f"mean forecast rmse (cycles 2+): ViT {f(vitr):.4f}, online {f(onl):.4f}, "
+          f"persistence {f(pers):.4f}")
+    assert f(vitr) < f(pers)
+    assert all(np.isfinite(onl.rmse)) and max(onl.rmse) < 3.0
