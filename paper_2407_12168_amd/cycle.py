@@ -53,7 +53,7 @@ class OnlineTuning:
     its gradient) lives on the observed components.  After each analysis the surrogate takes
     `steps` Adam steps at rate `lr`.  Needs the identity observation operator."""
     steps: int = 2
-    lr: float = 1e-5
+    lr: float = 3e-6
     window: int = 8
 
 
