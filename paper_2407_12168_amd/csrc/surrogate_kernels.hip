@@ -77,11 +77,27 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint16_t* in = args.in + (int64_t)b * H * W * CIN;
 
-  // all weights -> LDS
-  for (int v = tid; v < COUT * 9 * CIN / 8; v += 256) {
-    const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
-    *reinterpret_cast<u32x4*>(sW + co * LDW + k8 * 8) =
-        *reinterpret_cast<const u32x4*>(args.wk + (int64_t)co * 9 * CIN + k8 * 8);
+  // all weights -> LDS, every load of a thread issued before its stores (one memory latency
+  // per workgroup instead of one per 16-byte vector)
+  {
+    constexpr int kWV = COUT * 9 * CIN / 8, kWPer = (kWV + 255) / 256;
+    u32x4 wv[kWPer];
+#pragma unroll
+    for (int k = 0; k < kWPer; ++k) {
+      const int v = tid + k * 256;
+      if (v < kWV) {
+        const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
+        wv[k] = *reinterpret_cast<const u32x4*>(args.wk + (int64_t)co * 9 * CIN + k8 * 8);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kWPer; ++k) {
+      const int v = tid + k * 256;
+      if (v < kWV) {
+        const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
+        *reinterpret_cast<u32x4*>(sW + co * LDW + k8 * 8) = wv[k];
+      }
+    }
   }
   auto load_row = [&](int yy) {  // unwrapped row index -> ring slot yy mod 3
     const int slot = wrap(yy, 3);
@@ -123,9 +139,18 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
       }
     }
   };
-  load_row(y0 - 1);
-  load_row(y0);
-  load_row(y0 + 1);
+  if (prefetch) {
+    fetch_row(y0 - 1);
+    commit_row(y0 - 1);
+    fetch_row(y0);
+    commit_row(y0);
+    fetch_row(y0 + 1);
+    commit_row(y0 + 1);
+  } else {
+    load_row(y0 - 1);
+    load_row(y0);
+    load_row(y0 + 1);
+  }
   __syncthreads();
 
   float loss_local = 0.0f;
@@ -137,6 +162,28 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
       for (int tn = 0; tn < TN; ++tn)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[tn][r] = 0.0f;
+      // the epilogue's FP32 inputs (MODE 2: the pre-activation below; MODE 1: the residual
+      // and the target) are loaded before the MFMAs, so their latency overlaps them
+      float pre0[TN][16], pre1[TN][16];
+      if constexpr (MODE != 0) {
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+          const int co = tn * 32 + (lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int x = 32 * g + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            const int64_t pix = ((int64_t)b * H + y) * W + x;
+            pre0[tn][r] = pre1[tn][r] = 0.0f;
+            if constexpr (MODE == 2) {
+              pre0[tn][r] = args.u_prev[pix * COUT + co];
+            } else if (co < args.c0) {
+              const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
+              pre0[tn][r] = args.x_res[o];
+              if (args.target) pre1[tn][r] = args.target[o];
+            }
+          }
+        }
+      }
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
@@ -169,10 +216,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
           } else if constexpr (MODE == 1) {
             if (co < args.c0) {
               const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
-              const float yv = args.x_res[o] + v;
+              const float yv = pre0[tn][r] + v;
               args.y_out[o] = yv;
               if (args.target) {
-                const float diff = yv - args.target[o];
+                const float diff = yv - pre1[tn][r];
                 loss_local += diff * diff;
                 args.a_out[pix * COUT + co] = to_bf16(args.grad_scale * diff);
               }
@@ -180,7 +227,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
               args.a_out[pix * COUT + co] = 0;
             }
           } else {
-            const float gp = gelu_grad(args.u_prev[pix * COUT + co]);
+            const float gp = gelu_grad(pre0[tn][r]);
             args.a_out[pix * COUT + co] = to_bf16(v * gp);
           }
         }

@@ -42,7 +42,7 @@ def test_param_roundtrip_and_count(dev):
     sur.destroy()
 
 
-@pytest.mark.parametrize("h,w,batch", [(16, 32, 3), (128, 128, 2)])
+@pytest.mark.parametrize("h,w,batch", [(16, 32, 3), (13, 64, 2), (128, 128, 2)])
 def test_forward_matches_oracle(dev, h, w, batch):
     sur, params, x, _ = _setup(dev, h, w, batch, seed=1)
     xg = torch.from_numpy(x).to(dev)
@@ -71,14 +71,15 @@ def test_forward_in_chunks_larger_than_workspace(dev):
     sur.destroy()
 
 
-def test_gradients_match_oracle(dev):
-    sur, params, x, tgt = _setup(dev, 16, 32, 3, seed=4)
+@pytest.mark.parametrize("h,w,width", [(16, 32, 64), (13, 64, 32)])
+def test_gradients_match_oracle(dev, h, w, width):
+    sur, params, x, tgt = _setup(dev, h, w, 3, seed=4, width=width)
     grad = torch.empty(C.n_params(params), device=dev)
     loss = S.ensf_surrogate_grad(sur.handle, torch.from_numpy(x).to(dev),
                                  torch.from_numpy(tgt).to(dev), grad)
     want_loss, want = C.loss_and_grads(params, x.astype(np.float64), tgt.astype(np.float64))
     assert abs(loss - want_loss) <= 2e-2 * want_loss
-    g = C.unflatten(grad.cpu().numpy())
+    g = C.unflatten(grad.cpu().numpy(), width=width)
     for l, ((gw, gb), (ww, wb)) in enumerate(zip(g, want)):
         ew = np.linalg.norm(gw - ww) / np.linalg.norm(ww)
         eb = np.linalg.norm(gb - wb) / max(np.linalg.norm(wb), 1e-30)
