@@ -37,8 +37,10 @@ extern "C" {
 typedef struct ensf_surrogate ensf_surrogate;
 
 /* Creates a surrogate for C0-channel H x W states (C0 <= 32, width in {32, 64},
-   layers >= 2) with workspace for batches up to max_batch; parameters are initialised
-   from `seed` (He-normal, last layer scaled by 0.1, zero biases).  device: HIP ordinal. */
+   layers >= 2, W a multiple of 32, max_batch * H * W < 2^31) with workspace for batches up
+   to max_batch; parameters are initialised from `seed` (He-normal, last layer scaled by 0.1,
+   zero biases).  device: HIP ordinal.  Errors: ENSF_EINVAL (shape constraints above, out
+   NULL), ENSF_ENOMEM, ENSF_EHIP. */
 ensf_status ensf_surrogate_create(int32_t c0, int32_t width, int32_t layers, int32_t h,
                                   int32_t w, int32_t max_batch, uint64_t seed, int32_t device,
                                   ensf_surrogate** out);

@@ -17,7 +17,7 @@ using namespace ensf::sg;
 namespace {
 
 constexpr int kRows = 8;            // output rows per workgroup
-constexpr int kChunkPixels = 4096;  // pixels per weight-gradient partial
+constexpr int kChunkPixels = 2048;  // pixels per weight-gradient partial (one workgroup each)
 
 inline int pad_ch(int c) { return c <= 32 ? 32 : 64; }
 
@@ -186,7 +186,7 @@ ensf_status ensf_surrogate_create(int32_t c0, int32_t width, int32_t layers, int
   if (!out) return ENSF_EINVAL;
   *out = nullptr;
   if (c0 < 1 || c0 > 32 || (width != 32 && width != 64) || layers < 2 || h < 1 || w < 32 ||
-      w % 32 != 0 || max_batch < 1)
+      w % 32 != 0 || max_batch < 1 || (int64_t)max_batch * h * w > INT32_MAX)
     return ENSF_EINVAL;
   if (conv_smem_bytes(64, 64, w) + 1024 > 160 * 1024) return ENSF_EUNSUPPORTED;
   ensf::clear_stale_hip_error();

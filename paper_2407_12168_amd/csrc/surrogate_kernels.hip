@@ -252,104 +252,146 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
 }
 
 // ---------------------------------------------------------------------------------------
+constexpr int kWgradThreads = 512;
+
 // weight gradient: part[chunk][tap][co][ci] = sum_{p in chunk} du[p][co] * in[p + tap][ci]
 // on v_mfma_f32_32x32x16_bf16 (the operands are the BF16 activations and output gradients;
-// FP32 accumulation).  The contraction runs over pixels, which are strided in NHWC, so each
-// k-step of KS pixels is staged channel-major in LDS ([channel][pixel], rows padded to
-// KS + 8): a thread loads eight channels of two consecutive pixels (two 16-byte loads) and
-// writes the eight (pixel, pixel + 1) pairs as 4-byte words; a lane then reads the 8
-// consecutive pixels of its channel as one 16-byte fragment.
+// FP32 accumulation).  One workgroup computes all nine taps of its pixel chunk, so each k-step
+// stages the output-gradient tile once and the nine shifted input tiles beside it.  The
+// contraction runs over pixels, which are strided in NHWC, so each k-step of KS pixels is
+// staged channel-major in LDS ([channel][pixel], rows padded to KS + 8): a thread loads eight
+// channels of two consecutive pixels (two 16-byte loads) and writes the eight (pixel,
+// pixel + 1) pairs as 4-byte words; a lane then reads the 8 consecutive pixels of its channel
+// as one 16-byte fragment.  The 32 x 32 output blocks of one tap (COUT/32 x CIN/32 of them)
+// go to as many waves; the waves left over split the taps.  A k-step's loads are issued one
+// step ahead, during the previous step's MFMAs.
 
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs args) {
+__global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
+  constexpr int NT = kWgradThreads;
   constexpr int KS = 64;                  // pixels per k-step
   constexpr int LDK = KS + 8;             // LDS row (one channel), bf16
+  constexpr int WM = COUT / 32, WN = CIN / 32, NBLK = WM * WN;
+  constexpr int NGRP = NT / 64 / NBLK;    // wave groups splitting the taps
+  constexpr int NTAP = (9 + NGRP - 1) / NGRP;
   __shared__ __attribute__((aligned(16))) uint16_t sA[COUT * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[CIN * LDK];
-  constexpr int WM = COUT / 32, WN = CIN / 32;
+  __shared__ __attribute__((aligned(16))) uint16_t sB[9 * CIN * LDK];
   const int H = args.H, W = args.W;
-  const int chunk = blockIdx.x, tap = blockIdx.y;
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int chunk = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t npix = (int64_t)args.batch * H * W;
   const int64_t p0 = (int64_t)chunk * args.chunk_pixels;
   const int64_t p1 = min(p0 + (int64_t)args.chunk_pixels, npix);
-  const bool active = wave < WM * WN;
-  const int wm = wave / WN, wn = wave % WN;
+  const int blk = wave % NBLK, grp = wave / NBLK;
+  const int wm = blk / WN, wn = blk % WN;
 
-  // staging unit of this thread: pixel pair pp, channel octet c8.  A k-step's units are
-  // fetched into registers (fetch) one k-step ahead and written to LDS (put) after the
-  // previous k-step's MFMAs, so the loads overlap them.
-  constexpr int kNA = (KS / 2) * (COUT / 8), kNB = (KS / 2) * (CIN / 8);   // units per step
-  constexpr int kUA = (kNA + 255) / 256, kUB = (kNB + 255) / 256;
-  struct Units {
-    u32x4 a0[kUA], a1[kUA], b0[kUB], b1[kUB];
-  } u;
-  auto fetch_op = [&](u32x4* w0s, u32x4* w1s, int n, int total, auto src_of, int64_t pb) {
-    for (int k = 0; k < n; ++k) {
-      const int v = tid + k * 256;
-      if (v >= total) break;
-      const int pp = v % (KS / 2), c8 = v / (KS / 2);
-      u32x4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
-      const int64_t p = pb + 2 * pp;
-      if (p < p1) w0 = *reinterpret_cast<const u32x4*>(src_of(p) + c8 * 8);
-      if (p + 1 < p1) w1 = *reinterpret_cast<const u32x4*>(src_of(p + 1) + c8 * 8);
-      w0s[k] = w0;
-      w1s[k] = w1;
-    }
+  // staging units (pixel pair pp, channel octet c8; for B also the tap)
+  constexpr int kPairs = KS / 2;
+  constexpr int kNA = kPairs * (COUT / 8), kNB = 9 * kPairs * (CIN / 8);
+  constexpr int kUA = (kNA + NT - 1) / NT, kUB = (kNB + NT - 1) / NT;
+  u32x4 a0[kUA], a1[kUA], b0[kUB], b1[kUB];
+  // pixel p of the batch shifted by the tap, with periodic wrap (32-bit: the host keeps
+  // batch * H * W below 2^31)
+  auto in_row = [&](int64_t p, int tap) {
+    const int pi = (int)p, hw = H * W;
+    const int bimg = pi / hw, rem = pi - bimg * hw;
+    const int yy = rem / W, xx = rem - yy * W;
+    int ys = yy + tap / 3 - 1, xs = xx + tap % 3 - 1;
+    ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+    xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+    return args.in + ((int64_t)(bimg * H + ys) * W + xs) * CIN;
   };
-  auto put_op = [&](uint16_t* dst, const u32x4* w0s, const u32x4* w1s, int n, int total) {
-    for (int k = 0; k < n; ++k) {
-      const int v = tid + k * 256;
-      if (v >= total) break;
-      const int pp = v % (KS / 2), c8 = v / (KS / 2);
-      uint32_t* d = reinterpret_cast<uint32_t*>(dst + (c8 * 8) * LDK + 2 * pp);
+  auto fetch = [&](int64_t pb) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[(2 * q) * (LDK / 2)] = (w0s[k][q] & 0xFFFFu) | (w1s[k][q] << 16);
-        d[(2 * q + 1) * (LDK / 2)] = (w0s[k][q] >> 16) | (w1s[k][q] & 0xFFFF0000u);
+    for (int k = 0; k < kUA; ++k) {
+      const int v = tid + k * NT;
+      if (v < kNA) {
+        const int pp = v % kPairs, c8 = v / kPairs;
+        const int64_t p = pb + 2 * pp;
+        a0[k] = a1[k] = u32x4{0, 0, 0, 0};
+        if (p < p1) a0[k] = *reinterpret_cast<const u32x4*>(args.du + p * COUT + c8 * 8);
+        if (p + 1 < p1) a1[k] = *reinterpret_cast<const u32x4*>(args.du + (p + 1) * COUT + c8 * 8);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kUB; ++k) {
+      const int v = tid + k * NT;
+      if (v < kNB) {
+        const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
+        const int pp = rem % kPairs, c8 = rem / kPairs;
+        const int64_t p = pb + 2 * pp;
+        b0[k] = b1[k] = u32x4{0, 0, 0, 0};
+        if (p < p1) b0[k] = *reinterpret_cast<const u32x4*>(in_row(p, tap) + c8 * 8);
+        if (p + 1 < p1) b1[k] = *reinterpret_cast<const u32x4*>(in_row(p + 1, tap) + c8 * 8);
       }
     }
   };
-  auto du_row = [&](int64_t p) { return args.du + p * COUT; };
-  auto in_row = [&](int64_t p) {
-    const int64_t bimg = p / ((int64_t)H * W);
-    const int yy = (int)((p / W) % H), xx = (int)(p % W);
-    return args.in + ((bimg * H + wrap(yy + dy, H)) * W + wrap(xx + dx, W)) * CIN;
-  };
-
-  f32x16_t acc;
+  auto put_pair = [&](uint16_t* dst, const u32x4& w0, const u32x4& w1) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-
-  auto fetch = [&](int64_t pb) {
-    fetch_op(u.a0, u.a1, kUA, kNA, du_row, pb);
-    fetch_op(u.b0, u.b1, kUB, kNB, in_row, pb);
+    for (int q = 0; q < 4; ++q) {
+      d[(2 * q) * (LDK / 2)] = (w0[q] & 0xFFFFu) | (w1[q] << 16);
+      d[(2 * q + 1) * (LDK / 2)] = (w0[q] >> 16) | (w1[q] & 0xFFFF0000u);
+    }
   };
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < kUA; ++k) {
+      const int v = tid + k * NT;
+      if (v < kNA) {
+        const int pp = v % kPairs, c8 = v / kPairs;
+        put_pair(sA + (c8 * 8) * LDK + 2 * pp, a0[k], a1[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kUB; ++k) {
+      const int v = tid + k * NT;
+      if (v < kNB) {
+        const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
+        const int pp = rem % kPairs, c8 = rem / kPairs;
+        put_pair(sB + tap * CIN * LDK + (c8 * 8) * LDK + 2 * pp, b0[k], b1[k]);
+      }
+    }
+  };
+
+  f32x16_t acc[NTAP];
+#pragma unroll
+  for (int t = 0; t < NTAP; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+
   if (p0 < p1) fetch(p0);
   for (int64_t pb = p0; pb < p1; pb += KS) {
     __syncthreads();
-    put_op(sA, u.a0, u.a1, kUA, kNA);
-    put_op(sB, u.b0, u.b1, kUB, kNB);
+    put();
     __syncthreads();
     if (pb + KS < p1) fetch(pb + KS);
-    if (active) {
 #pragma unroll
-      for (int kk = 0; kk < KS; kk += 16) {
-        const int o = kk + (lane >> 5) * 8;
-        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(sA + (wm * 32 + (lane & 31)) * LDK + o);
-        const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(sB + (wn * 32 + (lane & 31)) * LDK + o);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < KS; kk += 16) {
+      const int o = kk + (lane >> 5) * 8;
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(sA + (wm * 32 + (lane & 31)) * LDK + o);
+#pragma unroll
+      for (int t = 0; t < NTAP; ++t) {
+        const int tap = grp + t * NGRP;
+        if (tap < 9) {
+          const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(
+              sB + tap * CIN * LDK + (wn * 32 + (lane & 31)) * LDK + o);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+        }
       }
     }
   }
-  if (active) {
-    float* out = args.part + ((int64_t)chunk * 9 + tap) * COUT * CIN;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int co = wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-      const int ci = wn * 32 + (lane & 31);
-      out[co * CIN + ci] = acc[r];
+  for (int t = 0; t < NTAP; ++t) {
+    const int tap = grp + t * NGRP;
+    if (tap < 9) {
+      float* out = args.part + ((int64_t)chunk * 9 + tap) * COUT * CIN;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int co = wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int ci = wn * 32 + (lane & 31);
+        out[co * CIN + ci] = acc[t][r];
+      }
     }
   }
 }
@@ -385,27 +427,32 @@ __global__ __launch_bounds__(256) void k_bias_grad_part(const uint16_t* __restri
   }
 }
 
-// grad[i] = sum over chunks of part[chunk][i] (fixed order), FP64 accumulation
-__global__ void k_reduce_chunks(const float* __restrict__ part, int64_t n, int chunks,
-                                float* __restrict__ grad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + i];
-  grad[i] = (float)s;
-}
-
-// wgrad partial layout [tap][co][ci] -> parameter layout [co][tap][ci]
-__global__ void k_reduce_wgrad(const float* __restrict__ part, int cout, int cin, int chunks,
-                               float* __restrict__ grad) {
-  const int64_t n = 9LL * cout * cin;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int tap = (int)(i / ((int64_t)cout * cin));
-  const int co = (int)((i / cin) % cout), ci = (int)(i % cin);
-  double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + i];
-  grad[((int64_t)co * 9 + tap) * cin + ci] = (float)s;
+// grad[i] = sum over chunks of part[chunk][i] in a fixed order, FP64 accumulation: a
+// workgroup takes 64 consecutive entries, its four thread groups the chunks g, g + 4, ...
+// (coalesced 256-byte rows), and the four group sums are added in group order.  WGRAD maps the
+// partial layout [tap][co][ci] to the parameter layout [co][tap][ci].
+template <bool WGRAD>
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int64_t n,
+                                                      int chunks, int cout, int cin,
+                                                      float* __restrict__ grad) {
+  __shared__ double sg[4][64];
+  const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + e;
+  double acc = 0.0;
+  if (i < n)
+    for (int c = g; c < chunks; c += 4) acc += part[(int64_t)c * n + i];
+  sg[g][e] = acc;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    const double t = ((sg[0][e] + sg[1][e]) + sg[2][e]) + sg[3][e];
+    if constexpr (WGRAD) {
+      const int tap = (int)(i / ((int64_t)cout * cin));
+      const int co = (int)((i / cin) % cout), ci = (int)(i % cin);
+      grad[((int64_t)co * 9 + tap) * cin + ci] = (float)t;
+    } else {
+      grad[i] = (float)t;
+    }
+  }
 }
 
 __global__ void k_sum_loss(const float* __restrict__ part, int n, double scale,
@@ -477,10 +524,10 @@ hipError_t launch_conv(int cin, int cout, int mode, const ConvArgs& a, hipStream
 }
 
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t s) {
-  dim3 grid(chunks, 9);
+  dim3 grid(chunks);
 #define SG_WG(CI, CO)                                                                \
   if (cin == CI && cout == CO) {                                                     \
-    hipLaunchKernelGGL((k_conv_wgrad<CI, CO>), grid, dim3(256), 0, s, a);            \
+    hipLaunchKernelGGL((k_conv_wgrad<CI, CO>), grid, dim3(kWgradThreads), 0, s, a);  \
     return hipGetLastError();                                                        \
   }
   SG_WG(32, 32) SG_WG(32, 64) SG_WG(64, 32) SG_WG(64, 64)
@@ -500,16 +547,16 @@ hipError_t launch_bias_grad(const uint16_t* du, int64_t npix, int cout, int chun
                             int chunks, float* part, float* grad, hipStream_t s) {
   hipLaunchKernelGGL(k_bias_grad_part, dim3(chunks), dim3(256), 0, s, du, npix, cout,
                      chunk_pixels, part);
-  hipLaunchKernelGGL(k_reduce_chunks, dim3((cout + 255) / 256), dim3(256), 0, s, part,
-                     (int64_t)cout, chunks, grad);
+  hipLaunchKernelGGL(k_reduce_parts<false>, dim3((cout + 63) / 64), dim3(256), 0, s, part,
+                     (int64_t)cout, chunks, cout, 1, grad);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_wgrad(const float* part, int cout, int cin, int chunks, float* grad,
                                hipStream_t s) {
   const int64_t n = 9LL * cout * cin;
-  hipLaunchKernelGGL(k_reduce_wgrad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                     cout, cin, chunks, grad);
+  hipLaunchKernelGGL(k_reduce_parts<true>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
+                     n, chunks, cout, cin, grad);
   return hipGetLastError();
 }
 
