@@ -188,7 +188,7 @@ ensf_status ensf_surrogate_create(int32_t c0, int32_t width, int32_t layers, int
   if (c0 < 1 || c0 > 32 || (width != 32 && width != 64) || layers < 2 || h < 1 || w < 32 ||
       w % 32 != 0 || max_batch < 1 || (int64_t)max_batch * h * w > INT32_MAX)
     return ENSF_EINVAL;
-  if (conv_smem_bytes(64, 64, w) + 1024 > 160 * 1024) return ENSF_EUNSUPPORTED;
+  if (conv_smem_bytes(64, 64, w, 1) + 1024 > 160 * 1024) return ENSF_EUNSUPPORTED;
   ensf::clear_stale_hip_error();
   HIP_TRY(hipSetDevice(device));
   ensf_surrogate* s = new ensf_surrogate();

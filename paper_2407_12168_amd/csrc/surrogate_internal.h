@@ -33,7 +33,8 @@ struct WgradArgs {
   int batch, H, W, chunk_pixels;
 };
 
-size_t conv_smem_bytes(int cin, int cout, int W);
+// Dynamic LDS of the convolution kernel with rp output rows per step (rp = 2 where it fits).
+size_t conv_smem_bytes(int cin, int cout, int W, int rp);
 hipError_t launch_conv(int cin, int cout, int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t s);
 hipError_t launch_pack_input(const float* x, uint16_t* a, int batch, int c0, int H, int W, int cp,

@@ -51,16 +51,31 @@ __global__ void k_pack_input(const float* __restrict__ x, uint16_t* __restrict__
   const int64_t npix = (int64_t)batch * H * W;
   if (p >= npix) return;
   const int64_t b = p / ((int64_t)H * W), yx = p % ((int64_t)H * W);
-  uint16_t* dst = a + p * CP;
-  for (int c = 0; c < CP; ++c)
-    dst[c] = c < c0 ? to_bf16(x[(b * c0 + c) * (int64_t)H * W + yx]) : (uint16_t)0;
+  // eight channels per 16-byte store (CP is 32 or 64)
+  u32x4* dst = reinterpret_cast<u32x4*>(a + p * CP);
+  for (int c8 = 0; c8 < CP / 8; ++c8) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c8 * 8 + 2 * q;
+      const uint32_t lo = c < c0 ? to_bf16(x[(b * c0 + c) * (int64_t)H * W + yx]) : 0u;
+      const uint32_t hi = c + 1 < c0 ? to_bf16(x[(b * c0 + c + 1) * (int64_t)H * W + yx]) : 0u;
+      w[q] = lo | (hi << 16);
+    }
+    dst[c8] = u32x4{w[0], w[1], w[2], w[3]};
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // implicit-GEMM convolution with fused epilogues
 
-template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
+// RP output rows per step: 4 * RP waves, wave w computes row y + w / 4 (its 32-pixel groups
+// w % 4, + 4, ...), with a ring of RP + 2 input rows in LDS.  RP = 2 keeps two waves per SIMD
+// (one can issue MFMAs while the other waits on LDS or memory) and halves the barriers per
+// row; it needs 4 input rows beside the weights in LDS, so wide rows use RP = 1.
+template <int CIN, int COUT, int MODE, int RP>
+__global__ __launch_bounds__(256 * RP) void k_conv(ConvArgs args) {
+  constexpr int NT = 256 * RP, NS = RP + 2;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   constexpr int LDW = 9 * CIN + 8;        // weight row (one output channel), bf16
   constexpr int LDI = CIN + 8;            // one halo pixel, bf16
@@ -69,22 +84,23 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
   uint16_t* sW = reinterpret_cast<uint16_t*>(smem_raw);
   uint16_t* sIn = sW + COUT * LDW;
   const int64_t row_elems = (int64_t)(W + 2) * LDI;
-  __shared__ float red[4];
+  __shared__ float red[4 * RP];
 
   const int b = blockIdx.y;
   const int y0 = blockIdx.x * args.rows;
   const int y1 = min(y0 + args.rows, H);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wrow = wave >> 2, wq = wave & 3;
   const uint16_t* in = args.in + (int64_t)b * H * W * CIN;
 
   // all weights -> LDS, every load of a thread issued before its stores (one memory latency
   // per workgroup instead of one per 16-byte vector)
   {
-    constexpr int kWV = COUT * 9 * CIN / 8, kWPer = (kWV + 255) / 256;
+    constexpr int kWV = COUT * 9 * CIN / 8, kWPer = (kWV + NT - 1) / NT;
     u32x4 wv[kWPer];
 #pragma unroll
     for (int k = 0; k < kWPer; ++k) {
-      const int v = tid + k * 256;
+      const int v = tid + k * NT;
       if (v < kWV) {
         const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
         wv[k] = *reinterpret_cast<const u32x4*>(args.wk + (int64_t)co * 9 * CIN + k8 * 8);
@@ -92,150 +108,163 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
     }
 #pragma unroll
     for (int k = 0; k < kWPer; ++k) {
-      const int v = tid + k * 256;
+      const int v = tid + k * NT;
       if (v < kWV) {
         const int co = v / (9 * CIN / 8), k8 = v % (9 * CIN / 8);
         *reinterpret_cast<u32x4*>(sW + co * LDW + k8 * 8) = wv[k];
       }
     }
   }
-  auto load_row = [&](int yy) {  // unwrapped row index -> ring slot yy mod 3
-    const int slot = wrap(yy, 3);
+  auto load_row = [&](int yy) {  // unwrapped row index -> ring slot yy mod NS
     const uint16_t* src = in + (int64_t)wrap(yy, H) * W * CIN;
-    uint16_t* dst = sIn + slot * row_elems;
-    for (int v = tid; v < (W + 2) * (CIN / 8); v += 256) {
+    uint16_t* dst = sIn + wrap(yy, NS) * row_elems;
+    for (int v = tid; v < (W + 2) * (CIN / 8); v += NT) {
       const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
       const int xs = wrap(xh - 1, W);
       *reinterpret_cast<u32x4*>(dst + xh * LDI + c8 * 8) =
           *reinterpret_cast<const u32x4*>(src + (int64_t)xs * CIN + c8 * 8);
     }
   };
-  // The next input row is fetched into registers before a row's MFMAs and written to its
-  // ring slot after them, so its memory latency overlaps the compute (rows of up to
-  // kPf * 256 16-byte vectors; longer rows are loaded after the compute instead).
-  constexpr int kPf = 8;
+  // The next RP input rows are fetched into registers before a step's MFMAs and written to
+  // their ring slots after them, so their memory latency overlaps the compute (rows of up to
+  // kPf * NT 16-byte vectors; longer rows are loaded after the compute instead).
+  constexpr int kPf = 8 / RP;
   const int row_vecs = (W + 2) * (CIN / 8);
-  const bool prefetch = row_vecs <= kPf * 256;
-  u32x4 pf[kPf];
-  auto fetch_row = [&](int yy) {
+  const bool prefetch = row_vecs <= kPf * NT;
+  u32x4 pf[RP][kPf];
+  auto fetch_row = [&](int j, int yy) {
     const uint16_t* src = in + (int64_t)wrap(yy, H) * W * CIN;
 #pragma unroll
     for (int k = 0; k < kPf; ++k) {
-      const int v = tid + k * 256;
+      const int v = tid + k * NT;
       if (v < row_vecs) {
         const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
-        pf[k] = *reinterpret_cast<const u32x4*>(src + (int64_t)wrap(xh - 1, W) * CIN + c8 * 8);
+        pf[j][k] = *reinterpret_cast<const u32x4*>(src + (int64_t)wrap(xh - 1, W) * CIN + c8 * 8);
       }
     }
   };
-  auto commit_row = [&](int yy) {
-    uint16_t* dst = sIn + wrap(yy, 3) * row_elems;
+  auto commit_row = [&](int j, int yy) {
+    uint16_t* dst = sIn + wrap(yy, NS) * row_elems;
 #pragma unroll
     for (int k = 0; k < kPf; ++k) {
-      const int v = tid + k * 256;
+      const int v = tid + k * NT;
       if (v < row_vecs) {
         const int xh = v / (CIN / 8), c8 = v % (CIN / 8);
-        *reinterpret_cast<u32x4*>(dst + xh * LDI + c8 * 8) = pf[k];
+        *reinterpret_cast<u32x4*>(dst + xh * LDI + c8 * 8) = pf[j][k];
       }
     }
   };
-  if (prefetch) {
-    fetch_row(y0 - 1);
-    commit_row(y0 - 1);
-    fetch_row(y0);
-    commit_row(y0);
-    fetch_row(y0 + 1);
-    commit_row(y0 + 1);
-  } else {
-    load_row(y0 - 1);
-    load_row(y0);
-    load_row(y0 + 1);
+  // rows y0 - 1 .. y0 + RP
+  for (int yy = y0 - 1; yy <= y0 + RP; ++yy) {
+    if (prefetch) {
+      fetch_row(0, yy);
+      commit_row(0, yy);
+    } else {
+      load_row(yy);
+    }
   }
   __syncthreads();
 
   float loss_local = 0.0f;
-  for (int y = y0; y < y1; ++y) {
-    if (prefetch && y + 1 < y1) fetch_row(y + 2);
-    for (int g = wave; g < W / 32; g += 4) {
-      f32x16_t acc[TN];
+  for (int ys = y0; ys < y1; ys += RP) {
+    const bool more = ys + RP < y1;       // a next step: its new rows ys + RP + 1 .. ys + 2 RP
+    if (prefetch && more)
 #pragma unroll
-      for (int tn = 0; tn < TN; ++tn)
+      for (int j = 0; j < RP; ++j) fetch_row(j, ys + RP + 1 + j);
+    const int y = ys + wrow;
+    if (y < y1) {
+      for (int g = wq; g < W / 32; g += 4) {
+        f32x16_t acc[TN];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[tn][r] = 0.0f;
-      // the epilogue's FP32 inputs (MODE 2: the pre-activation below; MODE 1: the residual
-      // and the target) are loaded before the MFMAs, so their latency overlaps them
-      float pre0[TN][16], pre1[TN][16];
-      if constexpr (MODE != 0) {
+        for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[tn][r] = 0.0f;
+        // the epilogue's FP32 inputs (MODE 2: the pre-activation below; MODE 1: the residual
+        // and the target) are loaded before the MFMAs, so their latency overlaps them
+        float pre0[TN][16], pre1[TN][16];
+        if constexpr (MODE != 0) {
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) {
+            const int co = tn * 32 + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int x = 32 * g + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+              const int64_t pix = ((int64_t)b * H + y) * W + x;
+              pre0[tn][r] = pre1[tn][r] = 0.0f;
+              if constexpr (MODE == 2) {
+                pre0[tn][r] = args.u_prev[pix * COUT + co];
+              } else if (co < args.c0) {
+                const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
+                pre0[tn][r] = args.x_res[o];
+                if (args.target) pre1[tn][r] = args.target[o];
+              }
+            }
+          }
+        }
+        auto tap_mfma = [&](int tap) {
+          const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+          const uint16_t* rowp = sIn + wrap(y + dy, NS) * row_elems +
+                                 (int64_t)(32 * g + (lane & 31) + dx + 1) * LDI + (lane >> 5) * 8;
+#pragma unroll
+          for (int c16 = 0; c16 < CIN / 16; ++c16) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(rowp + c16 * 16);
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+              const bf16x8_t bw = *reinterpret_cast<const bf16x8_t*>(
+                  sW + (tn * 32 + (lane & 31)) * LDW + tap * CIN + c16 * 16 + (lane >> 5) * 8);
+              acc[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[tn], 0, 0, 0);
+            }
+          }
+        };
+        // one wave per SIMD (RP = 1) can hold every fragment of the nine taps at once; with
+        // two waves per SIMD the taps are issued one at a time within the register budget
+        if constexpr (RP == 1) {
+#pragma unroll
+          for (int tap = 0; tap < 9; ++tap) tap_mfma(tap);
+        } else {
+#pragma unroll 1
+          for (int tap = 0; tap < 9; ++tap) tap_mfma(tap);
+        }
+        // epilogue: lane holds output channel co for 16 pixels of the group
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) {
           const int co = tn * 32 + (lane & 31);
+          const float bias = (MODE != 2 && args.bias) ? args.bias[co] : 0.0f;
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int x = 32 * g + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
             const int64_t pix = ((int64_t)b * H + y) * W + x;
-            pre0[tn][r] = pre1[tn][r] = 0.0f;
-            if constexpr (MODE == 2) {
-              pre0[tn][r] = args.u_prev[pix * COUT + co];
-            } else if (co < args.c0) {
-              const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
-              pre0[tn][r] = args.x_res[o];
-              if (args.target) pre1[tn][r] = args.target[o];
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const uint16_t* rowp = sIn + wrap(y + dy, 3) * row_elems +
-                               (int64_t)(32 * g + (lane & 31) + dx + 1) * LDI + (lane >> 5) * 8;
-#pragma unroll
-        for (int c16 = 0; c16 < CIN / 16; ++c16) {
-          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(rowp + c16 * 16);
-#pragma unroll
-          for (int tn = 0; tn < TN; ++tn) {
-            const bf16x8_t bw = *reinterpret_cast<const bf16x8_t*>(
-                sW + (tn * 32 + (lane & 31)) * LDW + tap * CIN + c16 * 16 + (lane >> 5) * 8);
-            acc[tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[tn], 0, 0, 0);
-          }
-        }
-      }
-      // epilogue: lane holds output channel co for 16 pixels of the group
-#pragma unroll
-      for (int tn = 0; tn < TN; ++tn) {
-        const int co = tn * 32 + (lane & 31);
-        const float bias = (MODE != 2 && args.bias) ? args.bias[co] : 0.0f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int x = 32 * g + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int64_t pix = ((int64_t)b * H + y) * W + x;
-          const float v = acc[tn][r] + bias;
-          if constexpr (MODE == 0) {
-            if (args.u_out) args.u_out[pix * COUT + co] = v;
-            args.a_out[pix * COUT + co] = to_bf16(gelu(v));
-          } else if constexpr (MODE == 1) {
-            if (co < args.c0) {
-              const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
-              const float yv = pre0[tn][r] + v;
-              args.y_out[o] = yv;
-              if (args.target) {
-                const float diff = yv - pre1[tn][r];
-                loss_local += diff * diff;
-                args.a_out[pix * COUT + co] = to_bf16(args.grad_scale * diff);
+            const float v = acc[tn][r] + bias;
+            if constexpr (MODE == 0) {
+              if (args.u_out) args.u_out[pix * COUT + co] = v;
+              args.a_out[pix * COUT + co] = to_bf16(gelu(v));
+            } else if constexpr (MODE == 1) {
+              if (co < args.c0) {
+                const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
+                const float yv = pre0[tn][r] + v;
+                args.y_out[o] = yv;
+                if (args.target) {
+                  const float diff = yv - pre1[tn][r];
+                  loss_local += diff * diff;
+                  args.a_out[pix * COUT + co] = to_bf16(args.grad_scale * diff);
+                }
+              } else if (args.target) {
+                args.a_out[pix * COUT + co] = 0;
               }
-            } else if (args.target) {
-              args.a_out[pix * COUT + co] = 0;
+            } else {
+              const float gp = gelu_grad(pre0[tn][r]);
+              args.a_out[pix * COUT + co] = to_bf16(v * gp);
             }
-          } else {
-            const float gp = gelu_grad(pre0[tn][r]);
-            args.a_out[pix * COUT + co] = to_bf16(v * gp);
           }
         }
       }
     }
-    __syncthreads();                      // all reads of row y-1's slot are done
-    if (y + 1 < y1) {
-      if (prefetch) commit_row(y + 2); else load_row(y + 2);
+    __syncthreads();                      // the rows ys - 1 .. ys + RP - 2 are no longer read
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < RP; ++j) {
+        if (prefetch) commit_row(j, ys + RP + 1 + j); else load_row(ys + RP + 1 + j);
+      }
       __syncthreads();
     }
   }
@@ -244,9 +273,11 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs args) {
       for (int o = 32; o > 0; o >>= 1) loss_local += __shfl_xor(loss_local, o);
       if (lane == 0) red[wave] = loss_local;
       __syncthreads();
-      if (tid == 0)
-        args.loss_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] =
-            red[0] + red[1] + red[2] + red[3];
+      if (tid == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < 4 * RP; ++w) t += red[w];
+        args.loss_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+      }
     }
   }
 }
@@ -494,28 +525,38 @@ __global__ void k_make_bf16_weights(const float* __restrict__ w, int cout, int c
 // ---------------------------------------------------------------------------------------
 // host launchers
 
-size_t conv_smem_bytes(int cin, int cout, int W) {
-  return (size_t)cout * (9 * cin + 8) * 2 + (size_t)3 * (W + 2) * (cin + 8) * 2;
+size_t conv_smem_bytes(int cin, int cout, int W, int rp) {
+  return (size_t)cout * (9 * cin + 8) * 2 + (size_t)(rp + 2) * (W + 2) * (cin + 8) * 2;
 }
 
-template <int CIN, int COUT, int MODE>
+// the dynamic LDS a workgroup may use on gfx950 (160 KB), less room for the static part
+constexpr size_t kMaxConvSmem = 159 * 1024;
+
+int conv_rows_per_step(int cin, int cout, int W) {
+  return conv_smem_bytes(cin, cout, W, 2) <= kMaxConvSmem ? 2 : 1;
+}
+
+template <int CIN, int COUT, int MODE, int RP>
 static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t s) {
-  const size_t shm = conv_smem_bytes(CIN, COUT, a.W);
+  const size_t shm = conv_smem_bytes(CIN, COUT, a.W, RP);
+  if (shm > kMaxConvSmem) return hipErrorInvalidValue;
   static size_t attr_bytes = 0;
   if (shm > 64 * 1024 && shm > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_conv<CIN, COUT, MODE>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_conv<CIN, COUT, MODE, RP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     attr_bytes = shm;
   }
   dim3 grid((a.H + a.rows - 1) / a.rows, a.batch);
-  hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), grid, dim3(256), shm, s, a);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, MODE, RP>), grid, dim3(256 * RP), shm, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_conv(int cin, int cout, int mode, const ConvArgs& a, hipStream_t s) {
-#define SG_CONV(CI, CO, MD) \
-  if (cin == CI && cout == CO && mode == MD) return launch_conv_t<CI, CO, MD>(a, s);
+  const int rp = conv_rows_per_step(cin, cout, a.W);
+#define SG_CONV(CI, CO, MD)                                                   \
+  if (cin == CI && cout == CO && mode == MD)                                  \
+    return rp == 2 ? launch_conv_t<CI, CO, MD, 2>(a, s) : launch_conv_t<CI, CO, MD, 1>(a, s);
   SG_CONV(32, 32, 0) SG_CONV(32, 64, 0) SG_CONV(64, 32, 0) SG_CONV(64, 64, 0)
   SG_CONV(32, 32, 1) SG_CONV(64, 32, 1)
   SG_CONV(32, 32, 2) SG_CONV(32, 64, 2) SG_CONV(64, 32, 2) SG_CONV(64, 64, 2)
