@@ -3,11 +3,12 @@
 // Activations are NHWC bf16 with the channel count padded to CP in {32, 64} (padding is
 // zero and stays zero: padded weights and biases are zero).  A 3x3 convolution with
 // periodic padding is an implicit GEMM: M = pixels, N = output channels, K = 9 taps x
-// input channels.  One workgroup (4 waves) owns one image and a band of output rows; it
-// keeps all weights and a ring of three input rows (with a one-pixel periodic halo) in
-// LDS, so each new output row costs one new input row from memory.  Wave w computes
-// 32-pixel groups w, w+4, ... of the row against all output channels with
-// v_mfma_f32_32x32x16_bf16 (FP32 accumulation).
+// input channels.  One workgroup owns one image and a band of output rows and computes RP
+// rows per step on 4 * RP waves (RP = 2 where LDS allows); it keeps all weights and a ring of
+// RP + 2 input rows (with a one-pixel periodic halo) in LDS, so each output row costs one new
+// input row from memory, fetched during the previous step.  Wave w computes 32-pixel groups
+// w % 4, + 4, ... of its row against all output channels with v_mfma_f32_32x32x16_bf16
+// (FP32 accumulation).
 //
 // The input-gradient convolution is the same kernel run on the output gradient with the
 // taps flipped and the weight matrix transposed.  The weight gradient contracts over
