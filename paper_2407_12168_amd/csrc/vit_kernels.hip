@@ -214,16 +214,29 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const flo
   extern __shared__ uint16_t tile[];   // kRows x (D + 2)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * kRows;
+  // the wave's next row is loaded while the current one is normalised
+  float nv[J][V];
+  auto fetch = [&](int64_t r) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) load_v<V>(x + r * D + d0, nv[j]);
+    }
+  };
+  fetch(r0 + wave);
   for (int rr = wave; rr < kRows; rr += 4) {
     const int64_t r = r0 + rr;
-    const float* xr = x + r * D;
     float v[J][V];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int c = 0; c < V; ++c) v[j][c] = nv[j][c];
+    if (rr + 4 < kRows) fetch(r + 4);
     float s = 0.0f;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int d0 = (j * 64 + lane) * V;
       if (d0 < D) {
-        load_v<V>(xr + d0, v[j]);
 #pragma unroll
         for (int c = 0; c < V; ++c) s += v[j][c];
       }
@@ -278,27 +291,56 @@ __global__ __launch_bounds__(256) void k_ln_bwd(const float* dy, const float* x,
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int c = 0; c < V; ++c) sg[j][c] = sb[j][c] = 0.0f;
+  float gm[J][V];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int d0 = (j * 64 + lane) * V;
+    if (d0 < D) load_v<V>(gam + d0, gm[j]);
+  }
+  // the wave's next row (dy, x, dres, statistics) is loaded while the current one is done
+  float ng[J][V], nx[J][V], no[J][V], nmu = 0.0f, nrs = 0.0f;
+  auto fetch = [&](int64_t r) {
+    nmu = mean[r];
+    nrs = rstd[r];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int d0 = (j * 64 + lane) * V;
+      if (d0 < D) {
+        load_v<V>(dy + r * D + d0, ng[j]);
+        load_v<V>(x + r * D + d0, nx[j]);
+        load_v<V>(dres + r * D + d0, no[j]);
+      }
+    }
+  };
+  fetch(r0 + wave * 8);
   for (int rr = wave * 8; rr < wave * 8 + 8; ++rr) {
     const int64_t r = r0 + rr;
-    const float mu = mean[r], rs = rstd[r];
+    const float mu = nmu, rs = nrs;
+    float g0[J][V], x0[J][V], o0[J][V];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        g0[j][c] = ng[j][c];
+        x0[j][c] = nx[j][c];
+        o0[j][c] = no[j][c];
+      }
+    if (rr + 1 < wave * 8 + 8) fetch(r + 1);
     float dv[J][V], xh[J][V];
     float s1 = 0.0f, s2 = 0.0f;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int d0 = (j * 64 + lane) * V;
       if (d0 < D) {
-        float g[V], xv[V], gm[V];
-        load_v<V>(dy + r * D + d0, g);
-        load_v<V>(x + r * D + d0, xv);
-        load_v<V>(gam + d0, gm);
 #pragma unroll
         for (int c = 0; c < V; ++c) {
-          xh[j][c] = (xv[c] - mu) * rs;
-          dv[j][c] = g[c] * gm[c];
+          const float g = g0[j][c];
+          xh[j][c] = (x0[j][c] - mu) * rs;
+          dv[j][c] = g * gm[j][c];
           s1 += dv[j][c];
           s2 += dv[j][c] * xh[j][c];
-          sg[j][c] += g[c] * xh[j][c];
-          sb[j][c] += g[c];
+          sg[j][c] += g * xh[j][c];
+          sb[j][c] += g;
         }
       }
     }
@@ -310,7 +352,8 @@ __global__ __launch_bounds__(256) void k_ln_bwd(const float* dy, const float* x,
       if (d0 < D) {
         float o[V];
         uint16_t h[V];
-        load_v<V>(dres + r * D + d0, o);
+#pragma unroll
+        for (int c = 0; c < V; ++c) o[c] = o0[j][c];
 #pragma unroll
         for (int c = 0; c < V; ++c) {
           o[c] += rs * (dv[j][c] - s1 - xh[j][c] * s2);
