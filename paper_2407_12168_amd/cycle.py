@@ -121,6 +121,8 @@ def run_cycle(cfg, forecast="sqg", surrogate=None, dev=None, log=None, online=No
 
     if forecast not in ("sqg", "conv", "vit", "persistence"):
         raise ValueError(forecast)
+    if forecast in ("conv", "vit") and surrogate is None:
+        raise ValueError(f"forecast '{forecast}' needs a trained surrogate")
     net_forward, net_train = _surrogate_ops(forecast, surrogate)
     if online is not None and net_train is None:
         raise ValueError("online training needs a learned forecast")

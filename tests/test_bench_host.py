@@ -59,3 +59,5 @@ def test_cycle_rejects_online_training_without_a_learned_forecast():
                         online=cycle.OnlineTuning())
     with pytest.raises(ValueError):
         cycle.run_cycle(cfg, "spectral")
+    with pytest.raises(ValueError):
+        cycle.run_cycle(cfg, "vit")
