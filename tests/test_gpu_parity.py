@@ -112,6 +112,21 @@ def test_score_parity_config2_shape(dev, precision, t):
     assert wsum <= 1e-5
 
 
+@pytest.mark.parametrize("t", [0.5, 0.01])
+def test_split_form_recovers_what_plain_bf16_loses(dev, t):
+    """The three forms on the same c2-shape score evaluation: plain BF16 operands (one product)
+    lose the cancellation in |x_j|^2 - 2 alpha x_j.x_k + alpha^2 |x_k|^2, amplified by 1/beta^2
+    in the logits; the split form (hi.hi + hi.lo + lo.hi) stays at FP32-level error."""
+    p = workloads.config_problem(2)
+    rows = [0, 1, 100, 255]
+    errs = {f: _score_case(dev, p, t, f, p.n_members, rows=rows)[0]
+            for f in ("fp32", "bf16x3", "bf16")}
+    print(f"c2 score t={t}: rel-L2 fp32 {errs['fp32']:.2e}, split {errs['bf16x3']:.2e}, "
+          f"plain BF16 {errs['bf16']:.2e}")
+    assert errs["bf16x3"] <= SCORE_TOL["bf16x3"]
+    assert errs["bf16"] > 10 * errs["bf16x3"]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_score_parity_config3_shape_sampled_rows(dev, precision):
     # full size (N = 1024, d = 131072); the oracle checks sampled particle rows
