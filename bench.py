@@ -170,19 +170,28 @@ def vit_training_flops(layers, tokens, embed, mlp_hidden, patch_dim, batch):
     return batch * (T * per_token + attn)
 
 
+# Table II rows this library can run (the 256^2 row has 4096 tokens, beyond its attention's
+# 1024): input size -> (layers, embed); patch 4, 8 heads, MLP ratio 4 throughout
+VIT_TABLE2 = {64: (12, 1024), 128: (24, 2048)}
+
+
 def run_vit_bench(a):
-    """Training throughput of the Table II 64^2 ViT surrogate (patch 4, 12 layers, 8 heads,
-    embed 1024, MLP ratio 4) on synthetic 2 x 64 x 64 states, as matrix-product TFLOP/s."""
+    """Training throughput of a Table II ViT surrogate (default the 64^2 row: patch 4, 12
+    layers, 8 heads, embed 1024, MLP ratio 4) on synthetic 2-level states, as matrix-product
+    TFLOP/s."""
     import torch
 
     from paper_2407_12168_amd import ensf, vit
     dev = torch.device("cuda:0")
     B = a.vit_batch
+    S = a.vit_size
+    L, D = VIT_TABLE2[S]
+    T = (S // 4) ** 2
     g = torch.Generator(device="cpu").manual_seed(2407)
-    x = torch.randn((B, 2, 64, 64), generator=g).to(dev)
+    x = torch.randn((B, 2, S, S), generator=g).to(dev)
     t = (x + 0.1 * torch.randn(x.shape, generator=g).to(dev)).contiguous()
-    m = vit.ViT(channels=2, height=64, width=64, patch=4, layers=12, heads=8, embed=1024,
-                mlp_hidden=4096, max_batch=B, seed=1)
+    m = vit.ViT(channels=2, height=S, width=S, patch=4, layers=L, heads=8, embed=D,
+                mlp_hidden=4 * D, max_batch=B, seed=1)
     h = m.handle
     for _ in range(a.warmup):
         vit.ensf_vit_train_step(h, x, t, 1e-4, want_loss=False)
@@ -195,7 +204,7 @@ def run_vit_bench(a):
     loss = vit.ensf_vit_train_step(h, x, t, 1e-4)
     n_params = vit.ensf_vit_num_params(h)
     m.destroy()
-    flops = vit_training_flops(12, 256, 1024, 4096, 32, B)
+    flops = vit_training_flops(L, T, D, 4 * D, 32, B)
     tf = flops / (ms * 1e-3) / 1e12
     rate = ensf.ensf_measure_mfma_rate("bf16")
     line = {
@@ -203,8 +212,8 @@ def run_vit_bench(a):
         "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": f"ViT 64x64 input, patch 4, 12 layers, 8 heads, embed 1024, "
-                               f"MLP 4096 ({n_params} parameters), batch {B}, forward + "
+        "config": {"workload": f"ViT {S}x{S} input, patch 4, {L} layers, 8 heads, embed {D}, "
+                               f"MLP {4 * D} ({n_params} parameters), batch {B}, forward + "
                                f"backward + Adam", "batch": B, "params": n_params},
         "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None,
@@ -358,6 +367,8 @@ def main():
     ap.add_argument("--vit", action="store_true",
                     help="time the Table II 64x64 ViT surrogate's training step instead")
     ap.add_argument("--vit-batch", type=int, default=32)
+    ap.add_argument("--vit-size", type=int, default=64, choices=sorted(VIT_TABLE2),
+                    help="Table II row by input size")
     ap.add_argument("--vit-cycle", action="store_true",
                     help="cycle with the Table II ViT as the forecast model (2x64x64 SQG; "
                          "--cycles, --epochs apply)")

@@ -94,17 +94,21 @@ def test_forward_loss_and_every_gradient_match_oracle(dev, case):
           ", ".join(f"{k} {v:.1e}" for k, v in sorted(worst.items(), key=lambda kv: -kv[1])[:6]))
 
 
-def test_one_layer_at_table2_widths_matches_oracle(dev):
-    """One transformer layer at the Table II 64^2 widths (embed 1024, 8 heads, MLP 4096), batch
-    1 (256 tokens): the products here use the large tiles (k-step 64, one and two LDS stages)
-    that the reduced configuration's short contractions never reach."""
-    cfg = V.Config(channels=2, height=64, width=64, patch=4, layers=1, heads=8, embed=1024,
-                   mlp_hidden=4096)
+@pytest.mark.parametrize("size", [64, 128])
+def test_one_layer_at_table2_widths_matches_oracle(dev, size):
+    """One transformer layer at the Table II widths, batch 1: 64^2 (embed 1024, 8 heads, MLP
+    4096, 256 tokens) and 128^2 (embed 2048, 8 heads, MLP 8192, 1024 tokens).  The products
+    here use the large tiles (k-step 64, one and two LDS stages) that the reduced
+    configuration's short contractions never reach; 128^2 also runs the widest LayerNorm and
+    the 1024-token attention rows."""
+    D = 1024 if size == 64 else 2048
+    cfg = V.Config(channels=2, height=size, width=size, patch=4, layers=1, heads=8, embed=D,
+                   mlp_hidden=4 * D)
     rng = np.random.default_rng(23)
     flat = V.init_params(cfg, rng)
     flat += 0.02 * rng.standard_normal(flat.size)
     flat = flat.astype(np.float32)
-    x = rng.standard_normal((1, 2, 64, 64)).astype(np.float32)
+    x = rng.standard_normal((1, 2, size, size)).astype(np.float32)
     target = (x + 0.3 * rng.standard_normal(x.shape)).astype(np.float32)
     f64 = flat.astype(np.float64)
     loss_ref, g_ref = V.loss_and_grad(cfg, f64, x.astype(np.float64), target.astype(np.float64))
@@ -126,7 +130,7 @@ def test_one_layer_at_table2_widths_matches_oracle(dev):
         tol = 5e-2 if name.startswith(("ln", "b_", "pos")) else 2e-2
         assert err < tol, (name, err)
         o += n
-    print("Table II widths, gradient rel-L2 per tensor: " +
+    print(f"Table II {size}^2 widths, gradient rel-L2 per tensor: " +
           ", ".join(f"{k} {v:.1e}" for k, v in sorted(worst.items(), key=lambda kv: -kv[1])[:6]))
 
 
