@@ -45,6 +45,7 @@ struct Layer {
 struct ensf_vit {
   ensf_vit_config cfg{};
   int T = 0, P = 0, D = 0, F = 0, Hh = 0, dh = 0, L = 0, B = 0;
+  int cus = 0;                // compute units of the device
   int64_t n_params = 0;
   int64_t pe_pos = 0, lnf_g = 0, lnf_b = 0;
   int pe = 0, head = 0;
@@ -74,6 +75,9 @@ struct ensf_vit {
   size_t kpart_floats = 0;
   double* rtmp = nullptr;     // group sums of the LayerNorm parameter gradients
   double *lossp = nullptr, *loss = nullptr;
+  // the optimizer step's segment table (device) and its workgroup count
+  AdamSeg* adam_segs = nullptr;
+  int n_adam_segs = 0, adam_blocks = 0;
 };
 
 namespace {
@@ -181,6 +185,45 @@ hipError_t allocate(ensf_vit* v) {
   A(&v->rtmp, (size_t)kSumGroups * D);
   A(&v->lossp, (size_t)loss_blocks(Ta * P));
   A(&v->loss, 1);
+  return e;
+}
+
+// The optimizer's segment table: the weight matrices (with their BF16 copies) and the plain
+// ranges between them, in parameter order.  Synchronous (at creation).
+hipError_t build_adam_table(ensf_vit* v) {
+  std::vector<AdamSeg> segs;
+  int blk = 0;
+  auto plain = [&](int64_t off, int64_t end) {
+    if (end <= off) return;
+    AdamSeg a{};
+    a.off = off;
+    a.len = end - off;
+    a.blk0 = blk;
+    blk += (int)((a.len + kAdamChunk - 1) / kAdamChunk);
+    segs.push_back(a);
+  };
+  int64_t cur = 0;
+  for (const Lin& l : v->lins) {
+    if (l.w < cur || l.out % 4 != 0 || l.in % 4 != 0) return hipErrorInvalidValue;
+    plain(cur, l.w);
+    AdamSeg a{};
+    a.off = l.w;
+    a.rows = l.out;
+    a.cols = l.in;
+    a.tiles_c = (l.in + kAdamTile - 1) / kAdamTile;
+    a.blk0 = blk;
+    a.w16 = l.w16;
+    a.w16t = l.w16t;
+    blk += a.tiles_c * ((l.out + kAdamTile - 1) / kAdamTile);
+    segs.push_back(a);
+    cur = l.w + (int64_t)l.out * l.in;
+  }
+  plain(cur, v->n_params);
+  hipError_t e = alloc(v, &v->adam_segs, segs.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(v->adam_segs, segs.data(), segs.size() * sizeof(AdamSeg), hipMemcpyHostToDevice);
+  v->n_adam_segs = (int)segs.size();
+  v->adam_blocks = blk;
   return e;
 }
 
@@ -331,14 +374,15 @@ hipError_t run_forward(ensf_vit* v, const float* x, const float* target, float* 
 
 // weight gradient dW = dY^T X from the transposed copies (rows x T_all each) and the bias
 // gradient from the row sums of dY^T.  The contraction runs over all tokens of the batch
-// while the output (out x in) may have few tiles: it is split so that about 1024
-// workgroups run, the partial products summed in split order (FP64) afterwards.
+// while the output (out x in) may have few tiles: it is split so that about three
+// workgroups per compute unit run (as many as are resident at once, so there is no partial
+// second round), the partial products summed in split order (FP64) afterwards.
 hipError_t weight_grad(ensf_vit* v, const Lin& l, const uint16_t* dyt, const uint16_t* xt,
                        int64_t Ta, hipStream_t s) {
   VGemm g = prod(mat(dyt, Ta), mat(xt, Ta), l.out, l.in, (int)Ta);
   const int tile = (l.out % 128 == 0 && l.in % 128 == 0) ? 128 : (l.out % 64 == 0 && l.in % 64 == 0) ? 64 : 32;
   const int64_t tiles = (int64_t)(l.out / tile) * (l.in / tile);
-  int splits = (int)std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, 1024 / tiles));
+  int splits = (int)std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, 3 * v->cus / tiles));
   while (splits > 1 && Ta / splits < 256) --splits;
   hipError_t e;
   if (splits > 1) {
@@ -511,8 +555,11 @@ ensf_status ensf_vit_create(const ensf_vit_config* cfg, ensf_vit** out) {
   if (c.device < 0 || c.device >= ndev) return ENSF_EINVAL;
   VIT_TRY(hipSetDevice(c.device));
   VIT_TRY(set_vit_smem_limit(c.embed, T));
+  int cus = 0;
+  VIT_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
   ensf_vit* v = new ensf_vit();
   v->cfg = c;
+  v->cus = std::max(cus, 1);
   v->T = T;
   v->P = P;
   v->D = c.embed;
@@ -523,6 +570,7 @@ ensf_status ensf_vit_create(const ensf_vit_config* cfg, ensf_vit** out) {
   v->B = c.max_batch;
   layout(v);
   hipError_t e = allocate(v);
+  if (e == hipSuccess) e = build_adam_table(v);
   if (e == hipSuccess) {
     // N(0, 0.02) weights and positions, zero biases, unit LayerNorm gains, head x 0.1
     std::vector<float> h(v->n_params, 0.0f);
@@ -612,8 +660,9 @@ ensf_status ensf_vit_train_step(ensf_vit* v, const float* d_x, const float* d_ta
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = (float)(1.0 - std::pow(0.9, (double)v->adam_step));
   const float bc2 = (float)(1.0 - std::pow(0.999, (double)v->adam_step));
-  VIT_TRY(launch_adam(v->w, v->g, v->m, v->v, v->n_params, lr, b1, b2, 1e-8f, bc1, bc2, s));
-  VIT_TRY(refresh_bf16(v, s));
+  const AdamArgs a{lr, b1, b2, 1e-8f, bc1, bc2};
+  VIT_TRY(launch_adam_bf16(v->adam_segs, v->n_adam_segs, v->adam_blocks, v->w, v->g, v->m, v->v,
+                           a, s));
   if (h_loss) {
     VIT_TRY(hipMemcpyAsync(h_loss, v->loss, sizeof(double), hipMemcpyDeviceToHost, s));
     VIT_TRY(hipStreamSynchronize(s));

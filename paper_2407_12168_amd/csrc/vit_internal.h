@@ -111,9 +111,27 @@ hipError_t launch_sum_batches(const float* src, int B, int T, int D, float* out,
 // FP32 (rows x cols) -> BF16 copy and BF16 transpose (cols x rows).
 hipError_t launch_to_bf16(const float* w, int rows, int cols, uint16_t* w16, uint16_t* w16t,
                           hipStream_t s);
-// Adam (bias-corrected) on n FP32 parameters.
-hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr,
-                       float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+// The optimizer step over the flat FP32 parameters, described by a device table of segments
+// in parameter order: a weight matrix (w16 set: rows x cols at off, cols and rows multiples
+// of 4, its BF16 copy w16 and transpose w16t rewritten from the updated weights), or a plain
+// range (w16 null: len parameters at off).  Segment k covers workgroups [blk0, next blk0):
+// ceil(rows / kAdamTile) * tiles_c for a matrix (tiles_c = ceil(cols / kAdamTile)),
+// ceil(len / kAdamChunk) for a range.
+constexpr int kAdamTile = 64, kAdamChunk = 4096;
+struct AdamSeg {
+  int64_t off, len;
+  int rows, cols, tiles_c, blk0;
+  uint16_t* w16;
+  uint16_t* w16t;
+};
+// Adam with bias correction: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// w -= lr (m / bc1) / (sqrt(v / bc2) + eps).
+struct AdamArgs {
+  float lr, b1, b2, eps, bc1, bc2;
+};
+hipError_t launch_adam_bf16(const AdamSeg* segs, int nseg, int nblocks, float* w,
+                           const float* g, float* m, float* v, const AdamArgs& a,
+                           hipStream_t s);
 // Raises the dynamic LDS limit of the row-wise kernels where embed D or T tokens need it.
 hipError_t set_vit_smem_limit(int D, int T);
 

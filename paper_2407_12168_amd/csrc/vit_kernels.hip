@@ -403,12 +403,20 @@ __global__ __launch_bounds__(256) void k_sum_rows_groups(const float* src, int64
   tmp[g * cols + c] = s;
 }
 
+// Second level: 64 columns per workgroup; wave w adds groups [w G / 4, (w + 1) G / 4) in
+// order (loads issued together), then the four wave sums are added in wave order.
 __global__ __launch_bounds__(256) void k_sum_groups(const double* tmp, int G, int64_t cols,
                                                     float* out, int accumulate) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int g = 0; g < G; ++g) s += tmp[g * cols + c];
+  if (c < cols)
+    for (int g = wave * G / 4; g < (wave + 1) * G / 4; ++g) s += tmp[g * cols + c];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave != 0 || c >= cols) return;
+  s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
   out[c] = accumulate ? (float)(out[c] + s) : (float)s;
 }
 
@@ -608,17 +616,78 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* w, int rows, int c
   }
 }
 
-__global__ __launch_bounds__(256) void k_adam(float* w, const float* g, float* m, float* v,
-                                              int64_t n, float lr, float b1, float b2, float eps,
-                                              float bc1, float bc2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+// Adam (bias-corrected) on one parameter.
+__device__ __forceinline__ void adam_update(float& w, float g, float& m, float& v,
+                                            const AdamArgs& a) {
+  m = a.b1 * m + (1.0f - a.b1) * g;
+  v = a.b2 * v + (1.0f - a.b2) * g * g;
+  w -= a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+}
+
+// The whole optimizer step in one grouped launch over a segment table.  A matrix segment is
+// done in tiles of kAdamTile x kAdamTile parameters: Adam on 16-byte groups of a row, then the
+// tile's BF16 copy row-major and, through LDS, transposed.  A plain range is done in chunks of
+// kAdamChunk parameters.
+__global__ __launch_bounds__(256) void k_adam_bf16(const AdamSeg* segs, int nseg, float* w,
+                                                   const float* g, float* m, float* v,
+                                                   AdamArgs a) {
+  __shared__ uint16_t t[kAdamTile][kAdamTile + 2];
+  const int blk = (int)blockIdx.x;
+  int lo = 0, hi = nseg - 1;          // the last segment that starts at or before blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].blk0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const AdamSeg sg = segs[lo];
+  const int local = blk - sg.blk0;
+  if (!sg.w16) {
+    const int64_t i0 = sg.off + (int64_t)local * kAdamChunk, end = sg.off + sg.len;
+    for (int j = 0; j < kAdamChunk / 256; ++j) {
+      const int64_t i = i0 + j * 256 + threadIdx.x;
+      if (i < end) {
+        float wi = w[i], mi = m[i], vi = v[i];
+        adam_update(wi, g[i], mi, vi, a);
+        w[i] = wi;
+        m[i] = mi;
+        v[i] = vi;
+      }
+    }
+    return;
+  }
+  const int r0 = (local / sg.tiles_c) * kAdamTile, c0 = (local % sg.tiles_c) * kAdamTile;
+  const int tc = (threadIdx.x & 15) * 4, tr = threadIdx.x >> 4;   // 16 threads per tile row
+  for (int p = 0; p < kAdamTile / 16; ++p) {
+    const int rl = p * 16 + tr, r = r0 + rl, c = c0 + tc;
+    if (r < sg.rows && c < sg.cols) {   // cols % 4 == 0: the four columns are inside
+      const int64_t i = sg.off + (int64_t)r * sg.cols + c;
+      float4 W = *reinterpret_cast<const float4*>(w + i);
+      float4 M = *reinterpret_cast<const float4*>(m + i);
+      float4 V = *reinterpret_cast<const float4*>(v + i);
+      const float4 G = *reinterpret_cast<const float4*>(g + i);
+      adam_update(W.x, G.x, M.x, V.x, a);
+      adam_update(W.y, G.y, M.y, V.y, a);
+      adam_update(W.z, G.z, M.z, V.z, a);
+      adam_update(W.w, G.w, M.w, V.w, a);
+      *reinterpret_cast<float4*>(w + i) = W;
+      *reinterpret_cast<float4*>(m + i) = M;
+      *reinterpret_cast<float4*>(v + i) = V;
+      const uint16_t h[4] = {to_bf16(W.x), to_bf16(W.y), to_bf16(W.z), to_bf16(W.w)};
+      *reinterpret_cast<uint2*>(sg.w16 + (int64_t)r * sg.cols + c) =
+          make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[rl][tc + k] = h[k];
+    }
+  }
+  __syncthreads();
+  // column c of the tile is rows r0.. of w16t's row c: two rows per 4-byte store (rows even)
+  for (int q = threadIdx.x; q < kAdamTile * (kAdamTile / 2); q += 256) {
+    const int cl = q / (kAdamTile / 2), pr = q % (kAdamTile / 2);
+    const int c = c0 + cl, r = r0 + 2 * pr;
+    if (c < sg.cols && r < sg.rows)
+      *reinterpret_cast<uint32_t*>(sg.w16t + (int64_t)c * sg.rows + r) =
+          (uint32_t)t[2 * pr][cl] | ((uint32_t)t[2 * pr + 1][cl] << 16);
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -724,7 +793,7 @@ hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out
     const int G = kSumGroups;
     hipLaunchKernelGGL(k_sum_rows_groups, dim3(blocks(cols, 256), G), dim3(256), 0, s, src, r,
                        cols, tmp);
-    hipLaunchKernelGGL(k_sum_groups, dim3(blocks(cols, 256)), dim3(256), 0, s, tmp, G, cols, out,
+    hipLaunchKernelGGL(k_sum_groups, dim3(blocks(cols, 64)), dim3(256), 0, s, tmp, G, cols, out,
                        accumulate ? 1 : 0);
     return hipGetLastError();
   }
@@ -795,10 +864,12 @@ hipError_t launch_to_bf16(const float* w, int rows, int cols, uint16_t* w16, uin
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr,
-                       float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(blocks(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, beta1,
-                     beta2, eps, bc1, bc2);
+hipError_t launch_adam_bf16(const AdamSeg* segs, int nseg, int nblocks, float* w,
+                           const float* g, float* m, float* v, const AdamArgs& a,
+                           hipStream_t s) {
+  if (nseg <= 0 || nblocks <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_adam_bf16, dim3((unsigned)nblocks), dim3(256), 0, s, segs, nseg, w, g, m,
+                     v, a);
   return hipGetLastError();
 }
 

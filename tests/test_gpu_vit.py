@@ -151,6 +151,32 @@ def test_adam_step_matches_oracle_adam_on_the_gpu_gradient(dev, case):
     assert _rel(step_got, step_want) < 1e-5
 
 
+@pytest.mark.parametrize("mlp_hidden", [128, 96])
+def test_optimizer_bf16_copies_equal_fresh_copies(dev, mlp_hidden):
+    # the optimizer step rewrites the BF16 weight copies (row-major and transposed) itself;
+    # they must equal the copies made from the FP32 weights it wrote (96: matrices that end
+    # in part-tiles of the optimizer's 64 x 64 tiles, as the 32-wide patch and head do)
+    cfg = V.Config(channels=2, height=32, width=32, patch=4, layers=2, heads=2, embed=64,
+                   mlp_hidden=mlp_hidden)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    x = torch.randn((BATCH, 2, 32, 32), generator=g).to(dev)
+    t = (x + 0.3 * torch.randn(x.shape, generator=g).to(dev)).contiguous()
+    with _model(cfg, BATCH, seed=2) as m:
+        n = vit.ensf_vit_num_params(m.handle)
+        for _ in range(3):
+            vit.ensf_vit_train_step(m.handle, x, t, 1e-3)
+        y1, g1 = torch.empty_like(x), torch.empty(n, device=dev)
+        vit.ensf_vit_forward(m.handle, x, y1)
+        vit.ensf_vit_grad(m.handle, x, t, g1)
+        vit.ensf_vit_set_params(m.handle, vit.ensf_vit_get_params(m.handle))
+        y2, g2 = torch.empty_like(x), torch.empty(n, device=dev)
+        vit.ensf_vit_forward(m.handle, x, y2)
+        vit.ensf_vit_grad(m.handle, x, t, g2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    assert torch.equal(g1, g2)
+
+
 def test_training_reduces_the_loss_at_the_reduced_and_table2_sizes(dev):
     # a learnable map: the increment is a third of the shift by one grid column
     for cfg, batch, steps, lr in ((CFG, BATCH, 30, 1e-4), (V.TABLE2_64, 2, 6, 2e-5)):
