@@ -20,7 +20,8 @@ namespace vit {
 
 namespace {
 
-constexpr int kRows = 32;   // rows per workgroup of the row-wise kernels (4 waves x 8)
+constexpr int kRows = 32;   // rows per workgroup of the row-wise kernels (four waves of eight
+                            // rows; eight waves of four in the LayerNorm forward)
 
 __device__ __forceinline__ uint16_t to_bf16(float v) {
   return __builtin_bit_cast(uint16_t, (__bf16)v);
@@ -207,10 +208,16 @@ __device__ __forceinline__ void store_bf16_v(uint16_t* p, const uint16_t (&h)[V]
   }
 }
 
+// Eight waves per kRows-row tile, rows strided by eight (two waves per SIMD at one
+// workgroup per CU).
+constexpr int kLnFwdWaves = 8;
+
 template <int V, int J>
-__global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const float* gam,
-                                                const float* bet, uint16_t* y, uint16_t* yt,
-                                                int64_t ld_t, float* mean, float* rstd) {
+__global__ __launch_bounds__(64 * kLnFwdWaves) void k_ln_fwd(const float* x, int D,
+                                                              const float* gam, const float* bet,
+                                                              uint16_t* y, uint16_t* yt,
+                                                              int64_t ld_t, float* mean,
+                                                              float* rstd) {
   extern __shared__ uint16_t tile[];   // kRows x (D + 2)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * kRows;
@@ -224,14 +231,14 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* x, int D, const flo
     }
   };
   fetch(r0 + wave);
-  for (int rr = wave; rr < kRows; rr += 4) {
+  for (int rr = wave; rr < kRows; rr += kLnFwdWaves) {
     const int64_t r = r0 + rr;
     float v[J][V];
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int c = 0; c < V; ++c) v[j][c] = nv[j][c];
-    if (rr + 4 < kRows) fetch(r + 4);
+    if (rr + kLnFwdWaves < kRows) fetch(r + kLnFwdWaves);
     float s = 0.0f;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -766,8 +773,8 @@ hipError_t launch_ln_fwd(const float* x, int64_t rows, int D, const float* gamma
   if (rows % kRows != 0 || D % 64 != 0 || D > 2048) return hipErrorInvalidValue;
   const size_t shm = yt ? (size_t)kRows * (D + 2) * 2 : 0;
   auto go = [&](auto kern, int) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)(rows / kRows)), dim3(256), shm, s, x, D, gamma,
-                       beta, y, yt, ld_t, mean, rstd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(rows / kRows)), dim3(64 * kLnFwdWaves), shm, s, x,
+                       D, gamma, beta, y, yt, ld_t, mean, rstd);
     return hipGetLastError();
   };
   VIT_LN_DISPATCH(k_ln_fwd, 0)
