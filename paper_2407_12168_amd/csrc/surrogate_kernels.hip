@@ -487,13 +487,21 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ 
   }
 }
 
-__global__ void k_sum_loss(const float* __restrict__ part, int n, double scale,
-                           double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
-  }
+// One wave: lane l adds the l-th of 64 consecutive slices of the partials in order (FP64),
+// then lane 0 adds the 64 slice sums in lane order.
+__global__ __launch_bounds__(64) void k_sum_loss(const float* __restrict__ part, int n,
+                                                double scale, double* __restrict__ out) {
+  __shared__ double sl[64];
+  const int l = threadIdx.x;
+  double s = 0.0;
+  for (int i = (int)((int64_t)l * n / 64); i < (int)((int64_t)(l + 1) * n / 64); ++i)
+    s += part[i];
+  sl[l] = s;
+  __syncthreads();
+  if (l != 0) return;
+  s = 0.0;
+  for (int k = 0; k < 64; ++k) s += sl[k];
+  *out = s * scale;
 }
 
 // Adam (Kingma & Ba, 2015) on the flat FP32 master parameters.

@@ -462,71 +462,109 @@ __global__ __launch_bounds__(256) void k_sum_batches(const float* src, int B, in
 // ----------------------------------------------------------------------------------------
 // attention rows
 
+// Attention rows of T values: lane l holds the V-wide groups (64 j + l) of a row (V = 4 when T
+// is a multiple of 256: 16-byte FP32 loads, 8-byte BF16 loads and stores).
+template <int V>
+__device__ __forceinline__ void load_bf16_v(const uint16_t* p, float (&v)[V]) {
+  if constexpr (V == 4) {
+    const uint2 w = *reinterpret_cast<const uint2*>(p);
+    v[0] = from_bf16((uint16_t)(w.x & 0xFFFFu));
+    v[1] = from_bf16((uint16_t)(w.x >> 16));
+    v[2] = from_bf16((uint16_t)(w.y & 0xFFFFu));
+    v[3] = from_bf16((uint16_t)(w.y >> 16));
+  } else {
+#pragma unroll
+    for (int c = 0; c < V; ++c) v[c] = from_bf16(p[c]);
+  }
+}
+
+template <int V>
 __global__ __launch_bounds__(256) void k_attn_softmax(const float* S, int T, uint16_t* P,
                                                       uint16_t* Pt) {
   extern __shared__ uint16_t tile[];   // kRows x (T + 2)
-  constexpr int kMaxJ = 1024 / 64;
+  constexpr int kMaxJ = 1024 / (64 * V);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t z = blockIdx.y;
   const int64_t q0 = (int64_t)blockIdx.x * kRows;
   const float* Sz = S + z * T * T;
   for (int rr = wave; rr < kRows; rr += 4) {
     const float* row = Sz + (q0 + rr) * T;
-    float v[kMaxJ];
+    float v[kMaxJ][V];
     float mx = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j)
-      if (j * 64 + lane < T) {
-        v[j] = row[j * 64 + lane];
-        mx = fmaxf(mx, v[j]);
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int c0 = (j * 64 + lane) * V;
+      if (c0 < T) {
+        load_v<V>(row + c0, v[j]);
+#pragma unroll
+        for (int c = 0; c < V; ++c) mx = fmaxf(mx, v[j][c]);
       }
+    }
     mx = wave_max(mx);
     float sum = 0.0f;
 #pragma unroll
     for (int j = 0; j < kMaxJ; ++j)
-      if (j * 64 + lane < T) {
-        v[j] = expf(v[j] - mx);
-        sum += v[j];
-      }
+      if ((j * 64 + lane) * V < T)
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          v[j][c] = expf(v[j][c] - mx);
+          sum += v[j][c];
+        }
     const float inv = 1.0f / wave_sum(sum);
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j)
-      if (j * 64 + lane < T) {
-        const uint16_t b = to_bf16(v[j] * inv);
-        P[z * T * T + (q0 + rr) * T + j * 64 + lane] = b;
-        tile[rr * (T + 2) + j * 64 + lane] = b;
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int c0 = (j * 64 + lane) * V;
+      if (c0 < T) {
+        uint16_t h[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          h[c] = to_bf16(v[j][c] * inv);
+          tile[rr * (T + 2) + c0 + c] = h[c];
+        }
+        store_bf16_v<V>(P + z * T * T + (q0 + rr) * T + c0, h);
       }
+    }
   }
   __syncthreads();
   store_tile_transposed(tile, T, Pt + z * T * T + q0, T);
 }
 
+template <int V>
 __global__ __launch_bounds__(256) void k_attn_ds(const uint16_t* P, const float* dP, int T,
                                                  float scale, uint16_t* dS, uint16_t* dSt) {
   extern __shared__ uint16_t tile[];   // kRows x (T + 2)
-  constexpr int kMaxJ = 1024 / 64;
+  constexpr int kMaxJ = 1024 / (64 * V);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t z = blockIdx.y;
   const int64_t q0 = (int64_t)blockIdx.x * kRows;
   for (int rr = wave; rr < kRows; rr += 4) {
     const int64_t o = z * T * T + (q0 + rr) * T;
-    float p[kMaxJ], g[kMaxJ];
+    float p[kMaxJ][V], g[kMaxJ][V];
     float dot = 0.0f;
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j)
-      if (j * 64 + lane < T) {
-        p[j] = from_bf16(P[o + j * 64 + lane]);
-        g[j] = dP[o + j * 64 + lane];
-        dot += p[j] * g[j];
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int c0 = (j * 64 + lane) * V;
+      if (c0 < T) {
+        load_bf16_v<V>(P + o + c0, p[j]);
+        load_v<V>(dP + o + c0, g[j]);
+#pragma unroll
+        for (int c = 0; c < V; ++c) dot += p[j][c] * g[j][c];
       }
+    }
     dot = wave_sum(dot);
 #pragma unroll
-    for (int j = 0; j < kMaxJ; ++j)
-      if (j * 64 + lane < T) {
-        const uint16_t b = to_bf16(scale * p[j] * (g[j] - dot));
-        dS[o + j * 64 + lane] = b;
-        tile[rr * (T + 2) + j * 64 + lane] = b;
+    for (int j = 0; j < kMaxJ; ++j) {
+      const int c0 = (j * 64 + lane) * V;
+      if (c0 < T) {
+        uint16_t h[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+          h[c] = to_bf16(scale * p[j][c] * (g[j][c] - dot));
+          tile[rr * (T + 2) + c0 + c] = h[c];
+        }
+        store_bf16_v<V>(dS + o + c0, h);
       }
+    }
   }
   __syncthreads();
   store_tile_transposed(tile, T, dSt + z * T * T + q0, T);
@@ -593,10 +631,20 @@ __global__ __launch_bounds__(256) void k_head_out(const float* tok, const float*
   if (threadIdx.x == 0) lossp[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_loss_final(const double* lossp, int n, double numel, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One wave: lane l adds the l-th of 64 consecutive slices of the partials in order, then lane
+// 0 adds the 64 slice sums in lane order.
+__global__ __launch_bounds__(64) void k_loss_final(const double* lossp, int n, double numel,
+                                                  double* out) {
+  __shared__ double part[64];
+  const int l = threadIdx.x;
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += lossp[i];
+  for (int i = (int)((int64_t)l * n / 64); i < (int)((int64_t)(l + 1) * n / 64); ++i)
+    s += lossp[i];
+  part[l] = s;
+  __syncthreads();
+  if (l != 0) return;
+  s = 0.0;
+  for (int k = 0; k < 64; ++k) s += part[k];
   *out = s / numel;
 }
 
@@ -754,8 +802,10 @@ hipError_t set_vit_smem_limit(int D, int T) {
   set(reinterpret_cast<const void*>(k_ln_bwd<4, 4>), ln);
   set(reinterpret_cast<const void*>(k_ln_bwd<4, 8>), ln);
   set(reinterpret_cast<const void*>(k_ln_bwd<1, 32>), ln);
-  set(reinterpret_cast<const void*>(k_attn_softmax), rows);
-  set(reinterpret_cast<const void*>(k_attn_ds), rows);
+  set(reinterpret_cast<const void*>(k_attn_softmax<4>), rows);
+  set(reinterpret_cast<const void*>(k_attn_softmax<1>), rows);
+  set(reinterpret_cast<const void*>(k_attn_ds<4>), rows);
+  set(reinterpret_cast<const void*>(k_attn_ds<1>), rows);
   return e;
 }
 
@@ -825,16 +875,24 @@ hipError_t launch_sum_batches(const float* src, int B, int T, int D, float* out,
 hipError_t launch_attn_softmax(const float* S, int64_t Z, int T, uint16_t* P, uint16_t* Pt,
                                hipStream_t s) {
   if (T % 64 != 0 || T > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_attn_softmax, dim3((unsigned)(T / kRows), (unsigned)Z), dim3(256),
-                     (size_t)kRows * (T + 2) * 2, s, S, T, P, Pt);
+  const dim3 grid((unsigned)(T / kRows), (unsigned)Z);
+  const size_t shm = (size_t)kRows * (T + 2) * 2;
+  if (T % 256 == 0)
+    hipLaunchKernelGGL(k_attn_softmax<4>, grid, dim3(256), shm, s, S, T, P, Pt);
+  else
+    hipLaunchKernelGGL(k_attn_softmax<1>, grid, dim3(256), shm, s, S, T, P, Pt);
   return hipGetLastError();
 }
 
 hipError_t launch_attn_ds(const uint16_t* P, const float* dP, int64_t Z, int T, float scale,
                           uint16_t* dS, uint16_t* dSt, hipStream_t s) {
   if (T % 64 != 0 || T > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_attn_ds, dim3((unsigned)(T / kRows), (unsigned)Z), dim3(256),
-                     (size_t)kRows * (T + 2) * 2, s, P, dP, T, scale, dS, dSt);
+  const dim3 grid((unsigned)(T / kRows), (unsigned)Z);
+  const size_t shm = (size_t)kRows * (T + 2) * 2;
+  if (T % 256 == 0)
+    hipLaunchKernelGGL(k_attn_ds<4>, grid, dim3(256), shm, s, P, dP, T, scale, dS, dSt);
+  else
+    hipLaunchKernelGGL(k_attn_ds<1>, grid, dim3(256), shm, s, P, dP, T, scale, dS, dSt);
   return hipGetLastError();
 }
 
