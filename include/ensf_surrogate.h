@@ -7,13 +7,14 @@
  * trained and run by its own HIP kernels:
  *
  *   y = x + net(x),  net = six 3x3 convolutions with periodic (circular) padding,
- *   channels C0 -> width -> ... -> width -> C0, exact erf-GELU between layers,
+ *   channels C0 -> width -> ... -> width -> C0, erf-GELU between layers (erf evaluated to
+ *   1.5e-7, below the BF16 rounding of the activations),
  *   trained on mean squared error with Adam (FP32 master weights).
  *
- * Numerics: weights and activations are BF16 in the forward and input-gradient
- * convolutions (BF16 MFMA, FP32 accumulation); the weight-gradient convolution reads the
- * same BF16 tensors and accumulates in FP32 MFMA; pre-activations, the output, the loss and
- * the optimizer state are FP32.
+ * Numerics: every convolution (forward, input gradient, weight gradient) has BF16 weight and
+ * activation operands and FP32 accumulation on MFMA; the GELU derivative at each hidden
+ * pre-activation is kept for the backward pass in BF16; pre-activations inside a kernel,
+ * the output, the loss, the gradient sums and the optimizer state are FP32.
  *
  * Layout: states are float32 NCHW (batch x C0 x H x W), i.e. one ensemble member of the
  * analysis is one C0 x H x W block (component e = c*H*W + y*W + x).  Parameters cross

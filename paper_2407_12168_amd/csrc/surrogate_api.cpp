@@ -42,10 +42,11 @@ struct ensf_surrogate {
   size_t nflat = 0, nbf = 0;
   float *d_param = nullptr, *d_grad = nullptr, *d_m = nullptr, *d_v = nullptr;
   uint16_t *d_wk = nullptr, *d_wf = nullptr;
-  // activations: act[l] = input of layer l (NHWC bf16, cinp[l] channels); u[l] = layer-l
-  // pre-activation (NHWC fp32, coutp[l]) for l < L-1; du ping-pong buffers (NHWC bf16)
+  // activations: act[l] = input of layer l (NHWC bf16, cinp[l] channels); gd[l] = GELU' at
+  // layer l's pre-activation (NHWC bf16, coutp[l]) for l < L-1, written by training forward
+  // passes; du ping-pong buffers (NHWC bf16)
   std::vector<uint16_t*> act;
-  std::vector<float*> u;
+  std::vector<uint16_t*> gd;
   uint16_t *du0 = nullptr, *du1 = nullptr;
   float *y_tmp = nullptr, *wpart = nullptr, *bpart = nullptr, *loss_part = nullptr;
   double* d_loss = nullptr;
@@ -67,7 +68,7 @@ void free_all(ensf_surrogate* s) {
     if (p) (void)hipFree(p);
   for (auto* p : s->act)
     if (p) (void)hipFree(p);
-  for (auto* p : s->u)
+  for (auto* p : s->gd)
     if (p) (void)hipFree(p);
 }
 
@@ -117,7 +118,7 @@ ensf_status forward_chunk(ensf_surrogate* s, const float* d_x, float* d_y, int b
     a.rows = kRows;
     a.c0 = s->c0;
     if (l < s->L - 1) {
-      a.u_out = d_target ? s->u[l] : nullptr;
+      a.gd_out = d_target ? s->gd[l] : nullptr;
       a.a_out = s->act[l + 1];
       HIP_TRY(launch_conv(s->cinp[l], s->coutp[l], 0, a, st));
     } else {
@@ -162,7 +163,7 @@ ensf_status gradient(ensf_surrogate* s, const float* d_x, const float* d_target,
       ConvArgs a{};
       a.in = du;
       a.wk = s->d_wf + s->wkoff[l];
-      a.u_prev = s->u[l - 1];
+      a.gd_prev = s->gd[l - 1];
       a.a_out = du_next;
       a.batch = batch;
       a.H = s->H;
@@ -224,10 +225,10 @@ ensf_status ensf_surrogate_create(int32_t c0, int32_t width, int32_t layers, int
   if (e == hipSuccess) e = hipMalloc(&s->d_wf, s->nbf * 2);
   const int64_t P = npix(s, max_batch);
   s->act.assign(layers, nullptr);
-  s->u.assign(layers, nullptr);
+  s->gd.assign(layers, nullptr);
   for (int l = 0; l < layers && e == hipSuccess; ++l) {
     e = hipMalloc(&s->act[l], (size_t)P * s->cinp[l] * 2);
-    if (e == hipSuccess && l < layers - 1) e = hipMalloc(&s->u[l], (size_t)P * s->coutp[l] * 4);
+    if (e == hipSuccess && l < layers - 1) e = hipMalloc(&s->gd[l], (size_t)P * s->coutp[l] * 2);
   }
   if (e == hipSuccess) e = hipMalloc(&s->du0, (size_t)P * 64 * 2);
   if (e == hipSuccess) e = hipMalloc(&s->du1, (size_t)P * 64 * 2);

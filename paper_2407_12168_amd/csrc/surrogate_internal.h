@@ -6,18 +6,18 @@
 namespace ensf {
 namespace sg {
 
-// Arguments of the implicit-GEMM convolution (k_conv).  MODE 0: hidden layer, writes the
-// pre-activation u_out (optional) and a_out = bf16(GELU(u)).  MODE 1: last layer, writes
-// y_out = x_res + u (NCHW, c0 channels) and, when target is set, the loss partials and the
-// bf16 output gradient grad_scale * (y - target) into a_out (NHWC).  MODE 2: input
-// gradient, a_out = bf16(acc * GELU'(u_prev)).
+// Arguments of the implicit-GEMM convolution (k_conv).  MODE 0: hidden layer, writes
+// a_out = bf16(GELU(u)) of the pre-activation u and, if gd_out is set (training), bf16(GELU'(u)).
+// MODE 1: last layer, writes y_out = x_res + u (NCHW, c0 channels) and, when target is set,
+// the loss partials and the bf16 output gradient grad_scale * (y - target) into a_out (NHWC).
+// MODE 2: input gradient, a_out = bf16(acc * gd_prev).
 struct ConvArgs {
   const uint16_t* in;       // NHWC bf16, CIN channels
   const uint16_t* wk;       // [COUT][9*CIN] bf16
   const float* bias;        // [COUT] or null
-  float* u_out;
+  uint16_t* gd_out;         // MODE 0, training: GELU' at the pre-activation (NHWC bf16)
   uint16_t* a_out;
-  const float* u_prev;
+  const uint16_t* gd_prev;  // MODE 2: the layer below's GELU' (NHWC bf16)
   const float* x_res;
   float* y_out;
   const float* target;

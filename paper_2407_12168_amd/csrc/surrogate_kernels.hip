@@ -34,13 +34,24 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
-__device__ __forceinline__ float gelu(float u) {
-  return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f));
-}
-__device__ __forceinline__ float gelu_grad(float u) {
-  const float cdf = 0.5f * (1.0f + erff(u * 0.70710678118654752f));
-  const float pdf = 0.3989422804014327f * expf(-0.5f * u * u);
-  return cdf + u * pdf;
+// GELU(u) = u Phi(u) and its derivative Phi(u) + u phi(u) from one exponential.  The normal
+// tail 1 - Phi(|u|) = erfc(|u| / sqrt 2) / 2 is taken from the rational form of
+// Abramowitz & Stegun 7.1.26, erfc(x) = (a1 t + ... + a5 t^5) exp(-x^2) with t = 1 / (1 + p x)
+// (|error| <= 1.5e-7), whose factor exp(-x^2) = exp(-u^2 / 2) is also sqrt(2 pi) phi(u); the
+// exponential and the reciprocal are the hardware's.  Both results are rounded to BF16 by
+// their users, far coarser than these errors.
+struct GeluPair {
+  float g, d;   // GELU(u), GELU'(u)
+};
+__device__ __forceinline__ GeluPair gelu_pair(float u) {
+  const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * (u * u));  // exp(-u^2 / 2)
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * 0.70710678118654752f * fabsf(u));
+  const float poly =
+      t * (0.254829592f +
+           t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float tail = 0.5f * poly * e;               // 1 - Phi(|u|)
+  const float cdf = u >= 0.0f ? 1.0f - tail : tail;
+  return {u * cdf, cdf + u * (0.3989422804014327f * e)};
 }
 
 __device__ __forceinline__ int wrap(int v, int n) { return ((v % n) + n) % n; }
@@ -193,7 +204,7 @@ __global__ __launch_bounds__(256 * RP) void k_conv(ConvArgs args) {
               const int64_t pix = ((int64_t)b * H + y) * W + x;
               pre0[tn][r] = pre1[tn][r] = 0.0f;
               if constexpr (MODE == 2) {
-                pre0[tn][r] = args.u_prev[pix * COUT + co];
+                pre0[tn][r] = from_bf16(args.gd_prev[pix * COUT + co]);
               } else if (co < args.c0) {
                 const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
                 pre0[tn][r] = args.x_res[o];
@@ -237,8 +248,9 @@ __global__ __launch_bounds__(256 * RP) void k_conv(ConvArgs args) {
             const int64_t pix = ((int64_t)b * H + y) * W + x;
             const float v = acc[tn][r] + bias;
             if constexpr (MODE == 0) {
-              if (args.u_out) args.u_out[pix * COUT + co] = v;
-              args.a_out[pix * COUT + co] = to_bf16(gelu(v));
+              const GeluPair gp = gelu_pair(v);
+              if (args.gd_out) args.gd_out[pix * COUT + co] = to_bf16(gp.d);
+              args.a_out[pix * COUT + co] = to_bf16(gp.g);
             } else if constexpr (MODE == 1) {
               if (co < args.c0) {
                 const int64_t o = (((int64_t)b * args.c0 + co) * H + y) * W + x;
@@ -253,8 +265,7 @@ __global__ __launch_bounds__(256 * RP) void k_conv(ConvArgs args) {
                 args.a_out[pix * COUT + co] = 0;
               }
             } else {
-              const float gp = gelu_grad(pre0[tn][r]);
-              args.a_out[pix * COUT + co] = to_bf16(v * gp);
+              args.a_out[pix * COUT + co] = to_bf16(v * pre0[tn][r]);
             }
           }
         }
