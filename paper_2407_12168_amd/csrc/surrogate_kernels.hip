@@ -18,6 +18,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "surrogate_internal.h"
 
 namespace ensf {
@@ -306,8 +308,8 @@ constexpr int kWgradThreads = 512;
 // channels of two consecutive pixels (two 16-byte loads) and writes the eight (pixel,
 // pixel + 1) pairs as 4-byte words; a lane then reads the 8 consecutive pixels of its channel
 // as one 16-byte fragment.  The 32 x 32 output blocks of one tap (COUT/32 x CIN/32 of them)
-// go to as many waves; the waves left over split the taps.  A k-step's loads are issued one
-// step ahead, during the previous step's MFMAs.
+// go to as many waves; the waves left over split the taps.  A k-step's loads are issued two
+// steps ahead (two register sets), so they have two steps' MFMAs to arrive in.
 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
@@ -332,28 +334,46 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
   constexpr int kPairs = KS / 2;
   constexpr int kNA = kPairs * (COUT / 8), kNB = 9 * kPairs * (CIN / 8);
   constexpr int kUA = (kNA + NT - 1) / NT, kUB = (kNB + NT - 1) / NT;
-  u32x4 a0[kUA], a1[kUA], b0[kUB], b1[kUB];
-  // pixel p of the batch shifted by the tap, with periodic wrap (32-bit: the host keeps
-  // batch * H * W below 2^31)
-  auto in_row = [&](int64_t p, int tap) {
-    const int pi = (int)p, hw = H * W;
-    const int bimg = pi / hw, rem = pi - bimg * hw;
-    const int yy = rem / W, xx = rem - yy * W;
+  // two register sets of staged vectors: a k-step's loads are issued two k-steps ahead (the
+  // loop is unrolled by two so that each set is a fixed set of registers)
+  u32x4 a0[2][kUA], a1[2][kUA], b0[2][kUB], b1[2][kUB];
+  // Pixel pb + off (off < KS) of the batch shifted by the tap, with periodic wrap, from the
+  // k-step's first pixel (bimg0, y00, x00): off < KS <= 2 W adds at most two rows (32-bit: the
+  // host keeps batch * H * W below 2^31).
+  int bimg0 = 0, y00 = 0, x00 = 0;
+  auto in_row = [&](int off, int tap) {
+    int bimg = bimg0, yy = y00, xx = x00 + off;
+    while (xx >= W) {
+      xx -= W;
+      if (++yy == H) {
+        yy = 0;
+        ++bimg;
+      }
+    }
     int ys = yy + tap / 3 - 1, xs = xx + tap % 3 - 1;
     ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
     xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
     return args.in + ((int64_t)(bimg * H + ys) * W + xs) * CIN;
   };
-  auto fetch = [&](int64_t pb) {
+  auto fetch = [&](auto set, int64_t pb) {
+    constexpr int S = decltype(set)::value;
+    {
+      const int pi = (int)pb, hw = H * W;
+      bimg0 = pi / hw;
+      const int rem = pi - bimg0 * hw;
+      y00 = rem / W;
+      x00 = rem - y00 * W;
+    }
 #pragma unroll
     for (int k = 0; k < kUA; ++k) {
       const int v = tid + k * NT;
       if (v < kNA) {
         const int pp = v % kPairs, c8 = v / kPairs;
         const int64_t p = pb + 2 * pp;
-        a0[k] = a1[k] = u32x4{0, 0, 0, 0};
-        if (p < p1) a0[k] = *reinterpret_cast<const u32x4*>(args.du + p * COUT + c8 * 8);
-        if (p + 1 < p1) a1[k] = *reinterpret_cast<const u32x4*>(args.du + (p + 1) * COUT + c8 * 8);
+        a0[S][k] = a1[S][k] = u32x4{0, 0, 0, 0};
+        if (p < p1) a0[S][k] = *reinterpret_cast<const u32x4*>(args.du + p * COUT + c8 * 8);
+        if (p + 1 < p1)
+          a1[S][k] = *reinterpret_cast<const u32x4*>(args.du + (p + 1) * COUT + c8 * 8);
       }
     }
 #pragma unroll
@@ -363,9 +383,10 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
         const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
         const int pp = rem % kPairs, c8 = rem / kPairs;
         const int64_t p = pb + 2 * pp;
-        b0[k] = b1[k] = u32x4{0, 0, 0, 0};
-        if (p < p1) b0[k] = *reinterpret_cast<const u32x4*>(in_row(p, tap) + c8 * 8);
-        if (p + 1 < p1) b1[k] = *reinterpret_cast<const u32x4*>(in_row(p + 1, tap) + c8 * 8);
+        b0[S][k] = b1[S][k] = u32x4{0, 0, 0, 0};
+        if (p < p1) b0[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp, tap) + c8 * 8);
+        if (p + 1 < p1)
+          b1[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp + 1, tap) + c8 * 8);
       }
     }
   };
@@ -377,13 +398,14 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
       d[(2 * q + 1) * (LDK / 2)] = (w0[q] >> 16) | (w1[q] & 0xFFFF0000u);
     }
   };
-  auto put = [&]() {
+  auto put = [&](auto set) {
+    constexpr int S = decltype(set)::value;
 #pragma unroll
     for (int k = 0; k < kUA; ++k) {
       const int v = tid + k * NT;
       if (v < kNA) {
         const int pp = v % kPairs, c8 = v / kPairs;
-        put_pair(sA + (c8 * 8) * LDK + 2 * pp, a0[k], a1[k]);
+        put_pair(sA + (c8 * 8) * LDK + 2 * pp, a0[S][k], a1[S][k]);
       }
     }
 #pragma unroll
@@ -392,7 +414,7 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
       if (v < kNB) {
         const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
         const int pp = rem % kPairs, c8 = rem / kPairs;
-        put_pair(sB + tap * CIN * LDK + (c8 * 8) * LDK + 2 * pp, b0[k], b1[k]);
+        put_pair(sB + tap * CIN * LDK + (c8 * 8) * LDK + 2 * pp, b0[S][k], b1[S][k]);
       }
     }
   };
@@ -403,12 +425,13 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
 
-  if (p0 < p1) fetch(p0);
-  for (int64_t pb = p0; pb < p1; pb += KS) {
+  // one k-step from register set `set`, whose refill (k-step pb + 2 KS) is issued before the
+  // MFMAs
+  auto step = [&](auto set, int64_t pb) {
     __syncthreads();
-    put();
+    put(set);
     __syncthreads();
-    if (pb + KS < p1) fetch(pb + KS);
+    if (pb + 2 * KS < p1) fetch(set, pb + 2 * KS);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 16) {
       const int o = kk + (lane >> 5) * 8;
@@ -423,6 +446,14 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
         }
       }
     }
+  };
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, 1>;
+  if (p0 < p1) fetch(Set0{}, p0);
+  if (p0 + KS < p1) fetch(Set1{}, p0 + KS);
+  for (int64_t pb = p0; pb < p1; pb += 2 * KS) {
+    step(Set0{}, pb);
+    if (pb + KS < p1) step(Set1{}, pb + KS);
   }
 #pragma unroll
   for (int t = 0; t < NTAP; ++t) {
