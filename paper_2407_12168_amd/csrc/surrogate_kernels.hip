@@ -298,6 +298,7 @@ __global__ __launch_bounds__(256 * RP) void k_conv(ConvArgs args) {
 
 // ---------------------------------------------------------------------------------------
 constexpr int kWgradThreads = 512;
+constexpr int kWgradStep = 64;     // pixels per k-step of the weight gradient
 
 // weight gradient: part[chunk][tap][co][ci] = sum_{p in chunk} du[p][co] * in[p + tap][ci]
 // on v_mfma_f32_32x32x16_bf16 (the operands are the BF16 activations and output gradients;
@@ -311,10 +312,15 @@ constexpr int kWgradThreads = 512;
 // go to as many waves; the waves left over split the taps.  A k-step's loads are issued two
 // steps ahead (two register sets), so they have two steps' MFMAs to arrive in.
 
-template <int CIN, int COUT>
+// HALO (W and the chunk a multiple of KS, so a k-step's pixels are KS consecutive pixels of
+// one image row): the nine tap tiles are built from three input row segments of KS + 2
+// pixels (rows y - 1, y, y + 1, columns x0 - 1 .. x0 + KS, periodic), each loaded once and
+// written at the three column shifts; the dx = 0 copy is one pixel off the pair boundary and
+// is written as 2-byte halves.  Otherwise each tap tile is loaded on its own.
+template <int CIN, int COUT, bool HALO>
 __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
   constexpr int NT = kWgradThreads;
-  constexpr int KS = 64;                  // pixels per k-step
+  constexpr int KS = kWgradStep;
   constexpr int LDK = KS + 8;             // LDS row (one channel), bf16
   constexpr int WM = COUT / 32, WN = CIN / 32, NBLK = WM * WN;
   constexpr int NGRP = NT / 64 / NBLK;    // wave groups splitting the taps
@@ -332,7 +338,9 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
 
   // staging units (pixel pair pp, channel octet c8; for B also the tap)
   constexpr int kPairs = KS / 2;
-  constexpr int kNA = kPairs * (COUT / 8), kNB = 9 * kPairs * (CIN / 8);
+  constexpr int kPairsH = KS / 2 + 1;      // HALO: pairs of a row segment of KS + 2 pixels
+  constexpr int kNA = kPairs * (COUT / 8);
+  constexpr int kNB = HALO ? 3 * kPairsH * (CIN / 8) : 9 * kPairs * (CIN / 8);
   constexpr int kUA = (kNA + NT - 1) / NT, kUB = (kNB + NT - 1) / NT;
   // two register sets of staged vectors: a k-step's loads are issued two k-steps ahead (the
   // loop is unrolled by two so that each set is a fixed set of registers)
@@ -376,17 +384,37 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
           a1[S][k] = *reinterpret_cast<const u32x4*>(args.du + (p + 1) * COUT + c8 * 8);
       }
     }
+    if constexpr (HALO) {
+      // pair m of row segment dyi: pixels x0 - 1 + 2m and x0 + 2m of row y + dyi - 1
 #pragma unroll
-    for (int k = 0; k < kUB; ++k) {
-      const int v = tid + k * NT;
-      if (v < kNB) {
-        const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
-        const int pp = rem % kPairs, c8 = rem / kPairs;
-        const int64_t p = pb + 2 * pp;
-        b0[S][k] = b1[S][k] = u32x4{0, 0, 0, 0};
-        if (p < p1) b0[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp, tap) + c8 * 8);
-        if (p + 1 < p1)
-          b1[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp + 1, tap) + c8 * 8);
+      for (int k = 0; k < kUB; ++k) {
+        const int v = tid + k * NT;
+        if (v < kNB) {
+          const int dyi = v / (kPairsH * (CIN / 8)), rem = v % (kPairsH * (CIN / 8));
+          const int m = rem % kPairsH, c8 = rem / kPairsH;
+          int ys = y00 + dyi - 1;
+          ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+          int xa = x00 - 1 + 2 * m, xb = xa + 1;
+          xa = xa < 0 ? xa + W : (xa >= W ? xa - W : xa);
+          xb = xb >= W ? xb - W : xb;
+          const uint16_t* row = args.in + (int64_t)(bimg0 * H + ys) * W * CIN + c8 * 8;
+          b0[S][k] = *reinterpret_cast<const u32x4*>(row + (int64_t)xa * CIN);
+          b1[S][k] = *reinterpret_cast<const u32x4*>(row + (int64_t)xb * CIN);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kUB; ++k) {
+        const int v = tid + k * NT;
+        if (v < kNB) {
+          const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
+          const int pp = rem % kPairs, c8 = rem / kPairs;
+          const int64_t p = pb + 2 * pp;
+          b0[S][k] = b1[S][k] = u32x4{0, 0, 0, 0};
+          if (p < p1) b0[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp, tap) + c8 * 8);
+          if (p + 1 < p1)
+            b1[S][k] = *reinterpret_cast<const u32x4*>(in_row(2 * pp + 1, tap) + c8 * 8);
+        }
       }
     }
   };
@@ -408,13 +436,43 @@ __global__ __launch_bounds__(kWgradThreads) void k_conv_wgrad(WgradArgs args) {
         put_pair(sA + (c8 * 8) * LDK + 2 * pp, a0[S][k], a1[S][k]);
       }
     }
+    if constexpr (HALO) {
+      // tile position k of tap (dyi, dx) holds segment pixel k + dx + 1: pair m is the pair at
+      // k = 2m of dx = -1 and at k = 2m - 2 of dx = +1, and pixels k = 2m - 1, 2m of dx = 0
 #pragma unroll
-    for (int k = 0; k < kUB; ++k) {
-      const int v = tid + k * NT;
-      if (v < kNB) {
-        const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
-        const int pp = rem % kPairs, c8 = rem / kPairs;
-        put_pair(sB + tap * CIN * LDK + (c8 * 8) * LDK + 2 * pp, b0[S][k], b1[S][k]);
+      for (int k = 0; k < kUB; ++k) {
+        const int v = tid + k * NT;
+        if (v < kNB) {
+          const int dyi = v / (kPairsH * (CIN / 8)), rem = v % (kPairsH * (CIN / 8));
+          const int m = rem % kPairsH, c8 = rem / kPairsH;
+          uint16_t* base = sB + (dyi * 3) * CIN * LDK + (c8 * 8) * LDK;
+          const u32x4& w0 = b0[S][k];
+          const u32x4& w1 = b1[S][k];
+          if (m < kPairsH - 1) put_pair(base + 2 * m, w0, w1);
+          if (m >= 1) put_pair(base + 2 * CIN * LDK + 2 * m - 2, w0, w1);
+          uint16_t* d0 = base + CIN * LDK;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (m >= 1) {
+              d0[(2 * q) * LDK + 2 * m - 1] = (uint16_t)(w0[q] & 0xFFFFu);
+              d0[(2 * q + 1) * LDK + 2 * m - 1] = (uint16_t)(w0[q] >> 16);
+            }
+            if (m < kPairsH - 1) {
+              d0[(2 * q) * LDK + 2 * m] = (uint16_t)(w1[q] & 0xFFFFu);
+              d0[(2 * q + 1) * LDK + 2 * m] = (uint16_t)(w1[q] >> 16);
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kUB; ++k) {
+        const int v = tid + k * NT;
+        if (v < kNB) {
+          const int tap = v / (kPairs * (CIN / 8)), rem = v % (kPairs * (CIN / 8));
+          const int pp = rem % kPairs, c8 = rem / kPairs;
+          put_pair(sB + tap * CIN * LDK + (c8 * 8) * LDK + 2 * pp, b0[S][k], b1[S][k]);
+        }
       }
     }
   };
@@ -617,10 +675,14 @@ hipError_t launch_conv(int cin, int cout, int mode, const ConvArgs& a, hipStream
 
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t s) {
   dim3 grid(chunks);
-#define SG_WG(CI, CO)                                                                \
-  if (cin == CI && cout == CO) {                                                     \
-    hipLaunchKernelGGL((k_conv_wgrad<CI, CO>), grid, dim3(kWgradThreads), 0, s, a);  \
-    return hipGetLastError();                                                        \
+  const bool halo = a.W % kWgradStep == 0 && a.chunk_pixels % kWgradStep == 0;
+#define SG_WG(CI, CO)                                                                        \
+  if (cin == CI && cout == CO) {                                                             \
+    if (halo)                                                                                \
+      hipLaunchKernelGGL((k_conv_wgrad<CI, CO, true>), grid, dim3(kWgradThreads), 0, s, a);  \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_conv_wgrad<CI, CO, false>), grid, dim3(kWgradThreads), 0, s, a); \
+    return hipGetLastError();                                                                \
   }
   SG_WG(32, 32) SG_WG(32, 64) SG_WG(64, 32) SG_WG(64, 64)
 #undef SG_WG

@@ -71,7 +71,7 @@ def test_forward_in_chunks_larger_than_workspace(dev):
     sur.destroy()
 
 
-@pytest.mark.parametrize("h,w,width", [(16, 32, 64), (13, 64, 32)])
+@pytest.mark.parametrize("h,w,width", [(16, 32, 64), (13, 64, 32), (13, 64, 64)])
 def test_gradients_match_oracle(dev, h, w, width):
     sur, params, x, tgt = _setup(dev, h, w, 3, seed=4, width=width)
     grad = torch.empty(C.n_params(params), device=dev)
