@@ -427,27 +427,41 @@ __global__ __launch_bounds__(256) void k_sum_groups(const double* tmp, int G, in
   out[c] = accumulate ? (float)(out[c] + s) : (float)s;
 }
 
+// One row per workgroup: thread t adds columns 8 t + 2048 j (16-byte loads, four issued
+// together), then the thread sums are added by wave (shuffle tree) and the four wave sums in
+// wave order.
 __global__ __launch_bounds__(256) void k_rowsum_bf16(const uint16_t* src, int64_t rows,
                                                      int64_t cols, int64_t ld, float* out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
+  __shared__ double red[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t row = blockIdx.x;
   double s = 0.0;
   const uint16_t* p = src + row * ld;
-  if ((cols & 7) == 0 && (ld & 7) == 0) {   // 8 values (16 bytes) per lane and load
-    for (int64_t c = lane * 8; c < cols; c += 512) {
-      const uint4 w = *reinterpret_cast<const uint4*>(p + c);
-      const uint32_t q[4] = {w.x, w.y, w.z, w.w};
-      float t = 0.0f;
+  auto add8 = [&](const uint4& w) {
+    const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+    float a = 0.0f;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t += from_bf16((uint16_t)(q[k] & 0xFFFFu)) + from_bf16((uint16_t)(q[k] >> 16));
-      s += t;
+    for (int k = 0; k < 4; ++k)
+      a += from_bf16((uint16_t)(q[k] & 0xFFFFu)) + from_bf16((uint16_t)(q[k] >> 16));
+    s += a;
+  };
+  if ((cols & 7) == 0 && (ld & 7) == 0) {   // 8 values (16 bytes) per thread and load
+    int64_t c = (int64_t)t * 8;
+    for (; c + 3 * 2048 < cols; c += 4 * 2048) {
+      uint4 w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = *reinterpret_cast<const uint4*>(p + c + u * 2048);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add8(w[u]);
     }
+    for (; c < cols; c += 2048) add8(*reinterpret_cast<const uint4*>(p + c));
   } else {
-    for (int64_t c = lane; c < cols; c += 64) s += from_bf16(p[c]);
+    for (int64_t c = t; c < cols; c += 256) s += from_bf16(p[c]);
   }
   s = wave_sum_d(s);
-  if (lane == 0) out[row] = (float)s;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (t == 0) out[row] = (float)(((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 __global__ __launch_bounds__(256) void k_sum_batches(const float* src, int B, int T, int D,
@@ -861,7 +875,8 @@ hipError_t launch_sum_rows(const float* src, int64_t r, int64_t cols, float* out
 
 hipError_t launch_rowsum_bf16(const uint16_t* src, int64_t rows, int64_t cols, int64_t ld,
                               float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowsum_bf16, dim3(blocks(rows, 4)), dim3(256), 0, s, src, rows, cols, ld,
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rowsum_bf16, dim3((unsigned)rows), dim3(256), 0, s, src, rows, cols, ld,
                      out);
   return hipGetLastError();
 }
