@@ -375,8 +375,8 @@ hipError_t run_forward(ensf_vit* v, const float* x, const float* target, float* 
 // weight gradient dW = dY^T X from the transposed copies (rows x T_all each) and the bias
 // gradient from the row sums of dY^T.  The contraction runs over all tokens of the batch
 // while the output (out x in) may have few tiles: it is split so that about three
-// workgroups per compute unit run (as many as are resident at once, so there is no partial
-// second round), the partial products summed in split order (FP64) afterwards.
+// workgroups per compute unit run (as many as are resident at once, so none waits for a
+// compute unit to free up), the partial products summed in split order (FP64) afterwards.
 hipError_t weight_grad(ensf_vit* v, const Lin& l, const uint16_t* dyt, const uint16_t* xt,
                        int64_t Ta, hipStream_t s) {
   VGemm g = prod(mat(dyt, Ta), mat(xt, Ta), l.out, l.in, (int)Ta);
