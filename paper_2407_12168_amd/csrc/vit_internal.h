@@ -55,14 +55,17 @@ enum VTile : int {
   kTile128pp = 2,       // 128 x 128, k-step 64, two stages
   kTile64 = 3,          // 64 x 64, waves of 32 x 32, k-step 32, two stages
   kTile32 = 4,          // 32 x 32 on one wave, k-step 32
-  kNumTiles = 5
+  kTile256 = 5,         // 256 x 128 on eight waves of 64 x 64, k-step 32, two stages
+  kNumTiles = 6
 };
 
 // M and N must be multiples of the chosen tile, K (and kchunk, when split) of its k-step.
 // Automatic choice by the contraction length per workgroup (kchunk when split): up to 256
 // (attention, patch embedding) 64 x 64 tiles, whose short k loops need the extra
 // workgroups; otherwise 128 x 128 where K is a multiple of 64 (two stages from 4096 on),
-// else 64 x 64, else 32 x 32.
+// else 64 x 64, else 32 x 32.  An unsplit, unbatched 128 x 128 choice with K >= 2048 becomes
+// 256 x 128 when that tile (two resident per CU) fills at least two per CU and its rounds of
+// resident workgroups are at least as full as those of 128 x 128 (three per CU).
 hipError_t launch_vgemm(const VGemm& g, int batch, hipStream_t s);
 
 // rows x D FP32 -> LayerNorm (population variance, eps 1e-5) -> BF16 rows y (ld D) and,

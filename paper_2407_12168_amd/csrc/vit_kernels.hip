@@ -71,10 +71,11 @@ __device__ __forceinline__ void store_tile_transposed(const uint16_t* tile, int 
 // C = alpha A B^T with the fused epilogue of VGemm.
 
 // Four-wave tiles are compiled for three resident waves per SIMD (three workgroups per CU,
-// whose LDS stages also fit): the register budget that leaves is enough without spills.
+// whose LDS stages also fit), eight-wave tiles for four (two workgroups per CU): the register
+// budgets that leaves are enough without spills.
 // BK is the k-step, ST the LDS stage count (2: ping-pong when both stages fit).
 template <int WGM, int WGN, int TM, int TN, int BK, int ST>
-__global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 4 ? 3 : 1)
+__global__ __launch_bounds__(64 * WGM * WGN, WGM * WGN >= 8 ? 4 : (WGM * WGN >= 4 ? 3 : 1))
 void k_vgemm(VGemm g) {
   constexpr int NT = 64 * WGM * WGN, BM = WGM * TM * 32, BN = WGN * TN * 32;
   using S = TileSmem<kBF16, BM, BN, BK, false>;
@@ -764,6 +765,21 @@ __global__ __launch_bounds__(256) void k_adam_bf16(const AdamSeg* segs, int nseg
 
 namespace {
 inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Compute units of the current device (looked up once per device).
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
 }
 
 hipError_t launch_vgemm(const VGemm& g0, int batch, hipStream_t s) {
@@ -789,12 +805,25 @@ hipError_t launch_vgemm(const VGemm& g0, int batch, hipStream_t s) {
     else if (m128 && keff % 64 == 0) tile = keff >= 4096 ? kTile128pp : kTile128;
     else if (m64) tile = kTile64;
     else tile = kTile32;
+    // 256 x 128 for unsplit contractions of 2048 or more where its rounds of resident
+    // workgroups (two per CU) are at least as full as those of 128 x 128 (three per CU); on
+    // shorter contractions its k-steps of 32 starve it
+    if ((tile == kTile128 || tile == kTile128pp) && g.splits == 1 && batch == 1 &&
+        g.M % 256 == 0 && g.K >= 2048) {
+      const int64_t cus = device_cus();
+      auto fill = [&](int64_t tiles, int64_t slots) {
+        return (double)tiles / (double)(((tiles + slots - 1) / slots) * slots);
+      };
+      const int64_t t256 = (int64_t)(g.M / 256) * (g.N / 128), t128 = 2 * t256;
+      if (t256 >= 2 * cus && fill(t256, 2 * cus) >= fill(t128, 3 * cus)) tile = kTile256;
+    }
   }
   switch (tile) {
     case kTile128: return go(k_vgemm<2, 2, 2, 2, 64, 1>, 128, 128, 64, 256);
     case kTile128pp: return go(k_vgemm<2, 2, 2, 2, 64, 2>, 128, 128, 64, 256);
     case kTile64: return go(k_vgemm<2, 2, 1, 1, 32, 2>, 64, 64, 32, 256);
     case kTile32: return go(k_vgemm<1, 1, 1, 1, 32, 2>, 32, 32, 32, 64);
+    case kTile256: return go(k_vgemm<4, 2, 2, 2, 32, 2>, 256, 128, 32, 512);
     default: return hipErrorInvalidValue;
   }
 }
